@@ -1,0 +1,392 @@
+/*
+ * prune.h -- C ABI of libprune_hip: PRUNE dynamic dataflow graphs whose
+ * signal-processing actors fire on an AMD Instinct MI355X (gfx950).
+ *
+ * Model of computation (Sec. III of Boutellier et al., "PRUNE: Dynamic and
+ * Decidable Dataflow for Signal Processing on Heterogeneous Platforms"):
+ * an application is a graph G = (A, F) of actors and FIFOs.  Ports are
+ * control input ports (rate 1), static regular ports (SRP, one fixed rate) or
+ * dynamic regular ports (DRP, rate atr or 0).  Each FIFO has one rate
+ * (fiforate) that must equal the atr of both its ports, and a delay (initial
+ * tokens).  A configuration actor emits control tokens; a dynamic actor
+ * consumes one per firing and sets each DRP to atr or 0 per Eq. 1 through the
+ * control table.  FIFO capacity is fixed by Eq. 2 with the compile-time
+ * constant C (C = 2 double buffer, C = 3 triple buffer); channels with delay
+ * follow the access pattern described with Fig. 6.
+ *
+ * Conventions for every entry point:
+ *  - returns PRUNE_OK (0) or a negative prune_status; prune_last_error()
+ *    gives a thread-local description of the last failure;
+ *  - "device pointer" means memory on the graph's HIP device (for example a
+ *    torch CUDA/HIP tensor's data_ptr()); "host pointer" means CPU memory;
+ *  - host arrays are copied before the call returns; device buffers passed
+ *    to *_bind_* calls are borrowed and must outlive the graph; buffers passed
+ *    as sources of copies may be reused once the stream has passed the call;
+ *  - all calls on one graph come from one host thread; device work is
+ *    enqueued on the given hipStream_t (0 = the null stream) and asynchronous
+ *    device errors surface at prune_graph_sync();
+ *  - complex samples are complex64: interleaved (re, im) float32 pairs.
+ */
+#ifndef PRUNE_H
+#define PRUNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct prune_graph *prune_graph_t;
+typedef int32_t prune_status;
+typedef uint32_t prune_id;
+typedef void *prune_stream_t; /* a hipStream_t */
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+  PRUNE_OK = 0,
+  PRUNE_E_ARG = -1,           /* bad argument or id                           */
+  PRUNE_E_STATE = -2,         /* call not allowed in this state (e.g. edit
+                                 after finalize, fire before finalize)        */
+  PRUNE_E_RATE_MISMATCH = -3, /* atr(p) != fiforate(fifo(p)) (Sec. III-A), or
+                                 an actor's rate relation does not hold       */
+  PRUNE_E_PORT_KIND = -4,     /* control port rate != 1, control output port
+                                 not an SRP of rate 1 feeding control ports,
+                                 DRP on a static actor, dynamic actor without
+                                 exactly one control port, DRP not controlled
+                                 by the port feeding its actor (Sec. III-B/C) */
+  PRUNE_E_RULE4 = -5,         /* dynamic inputs and outputs on one actor
+                                 (single-sided dynamism rule, Sec. IV)        */
+  PRUNE_E_CONNECT = -6,       /* input port without exactly one FIFO, output
+                                 port without a FIFO, wrong direction         */
+  PRUNE_E_DELAY = -7,         /* delay that the Eq. 2 buffer cannot hold     */
+  PRUNE_E_TOKEN = -8,         /* control value with elements beyond its
+                                 declared size, rate outside 1..atr, block
+                                 count differing from the firing's rate      */
+  PRUNE_E_DEADLOCK = -9,      /* no actor can fire while input is pending    */
+  PRUNE_E_CAPACITY = -10,     /* bound storage smaller than Eq. 2's capacity */
+  PRUNE_E_HIP = -11,          /* HIP runtime error (text in last_error)      */
+  PRUNE_E_UNSUPPORTED = -12   /* shape beyond the kernels' limits            */
+};
+
+enum { PRUNE_IN = 0, PRUNE_OUT = 1 };
+enum { PRUNE_SRP = 0, PRUNE_DRP = 1, PRUNE_CPORT = 2 };
+
+/* Port flags.  PRUNE_PORT_PARAM: the port moves the firing's rate parameter
+ * (carried by the control token, or the frame length for a source) plus the
+ * port's halo instead of its atr; atr is then the maximum.  With the
+ * parameter equal to atr this is Eq. 1 unchanged. */
+enum { PRUNE_PORT_PARAM = 1u };
+
+/* Actor kinds.
+ *  SOURCE      one output port; frames arrive through prune_source_push.
+ *  CONFIG      configuration actor: control output ports (SRP, rate 1) that
+ *              broadcast one control token per firing, computed from
+ *              external side-information (prune_config_push).
+ *  FILTERBANK  the merged dynamic processing graph of the DPD application
+ *              (poly -> FIR_b -> add, Sec. VII-A): one data input, one data
+ *              output, an optional control port.  Branch d is the DC whose
+ *              DRPs are addressed by prune_filterbank_branch(); it computes
+ *              sum_l h_d[l] |x[n-l]|^p x[n-l], p = d mod Kmax.
+ *  SWITCH      dynamic actor x: one SRP input, DRP outputs; an active output
+ *              port receives the frame preceded by `halo` past samples.
+ *  SELECT      dynamic actor y: DRP inputs, one SRP output = sum of active
+ *              inputs (the active input for one-hot control values).
+ *  PASSTHROUGH static copy actor.
+ *  SINK        one input port. */
+enum {
+  PRUNE_SOURCE = 0,
+  PRUNE_CONFIG = 1,
+  PRUNE_FILTERBANK = 2,
+  PRUNE_SWITCH = 3,
+  PRUNE_SELECT = 4,
+  PRUNE_PASSTHROUGH = 5,
+  PRUNE_SINK = 6
+};
+
+/* Execution modes of prune_graph_fire. */
+enum {
+  PRUNE_PER_FIRING = 0,    /* one launch sequence per actor firing, in
+                              round-robin actor order (the runtime model of
+                              Sec. VI-C, one firing at a time)            */
+  PRUNE_BATCHED = 1,       /* all firings of B graph iterations in a fixed
+                              launch sequence with one persistent
+                              filter-bank launch                          */
+  PRUNE_BATCHED_GRAPH = 2  /* BATCHED, captured once per batch size as a
+                              hipGraph and replayed                       */
+};
+
+/* Configuration actor modes (how side-information becomes a control value). */
+enum {
+  PRUNE_CONFIG_PREFIX = 0, /* mask = ((1 << K) - 1) << (bank * Kmax)        */
+  PRUNE_CONFIG_ROUTE = 1   /* mask = 1 << route (one-hot DC selection)     */
+};
+
+/* Control token (8 bytes): the control value v (bit e-1 = element e) and
+ * the rate parameter of the firing. */
+typedef struct {
+  uint32_t mask;
+  uint32_t rate;
+} prune_ctrl_token;
+
+/* External side-information of one configuration-actor firing. */
+typedef struct {
+  uint32_t K;     /* active branches (prefix mode)                          */
+  uint32_t n;     /* frame length = rate parameter of the token             */
+  uint32_t bank;  /* tap bank (prefix mode)                                 */
+  uint32_t route; /* DC index (route mode)                                  */
+} prune_side_info;
+
+typedef struct {
+  uint32_t mode;       /* PRUNE_CONFIG_PREFIX or PRUNE_CONFIG_ROUTE         */
+  uint32_t Kmax;       /* branches per bank (prefix mode)                    */
+  uint32_t n_elements; /* |v|: number of elements of the control value      */
+} prune_config_params;
+
+#define PRUNE_MAX_BANKS 4
+#define PRUNE_MAX_BRANCHES 32 /* n_banks * Kmax <= 32 (one mask word)     */
+#define PRUNE_MAX_L 64        /* taps per branch                           */
+
+typedef struct {
+  uint32_t n_banks;               /* 1..PRUNE_MAX_BANKS                     */
+  uint32_t Kmax;                  /* branches per bank, 1..10               */
+  uint32_t L[PRUNE_MAX_BANKS];    /* taps per branch of each bank, 1..64    */
+  uint32_t windowed;              /* 0: stateful -- the actor keeps the
+                                     last Lmax-1 input samples of its stream;
+                                     1: stateless -- each input block holds
+                                     Lmax-1 past samples, then the frame    */
+  uint32_t fixed_mask;            /* branch mask used when the actor has no
+                                     control port                          */
+} prune_fb_params;
+
+typedef struct {
+  uint64_t writes, reads;                 /* firings that wrote / read     */
+  uint64_t tokens_written, tokens_read;   /* tokens moved (delays excluded) */
+  uint64_t max_occ;                       /* largest occupancy seen (tokens,
+                                             delays included; depends on
+                                             the schedule)                   */
+  uint64_t capacity;                      /* Eq. 2 in tokens               */
+} prune_fifo_stats;
+
+/* Per-firing trace records (prune_trace_fetch), 8 x uint32 each.
+ *  type 0 = FIFO access: a = fifo, b = op (0 write, 1 read), c = firing
+ *           number of the accessing actor, d = write/read index, e = first
+ *           slot, f = token count;
+ *  type 1 = control decode of a dynamic actor: a = actor, c = firing,
+ *           d = control value (mask), e = rate parameter, f = bitmap of
+ *           DRPs set to atr (bit i = i-th DRP of the actor). */
+typedef struct {
+  uint32_t type, a, b, c, d, e, f, pad;
+} prune_trace_record;
+
+/* ---- graph construction (Sec. III-A/B) --------------------------------- */
+
+/* Create an empty graph on HIP device `hip_device`.  *out receives the
+ * handle.  E_HIP if the device cannot be selected.  hip_device = -1 creates
+ * a host-only graph: construction, validation and Eq. 2 sizing work, device
+ * calls (binding, pushing, firing) return E_STATE. */
+prune_status prune_graph_create(int hip_device, prune_graph_t *out);
+
+/* Free the graph's library-owned memory (metadata, taps, histories, work
+ * lists).  Borrowed FIFO storage is not freed.  Waits for the device. */
+prune_status prune_graph_destroy(prune_graph_t g);
+
+/* Add an actor.  params: prune_config_params for CONFIG, prune_fb_params for
+ * FILTERBANK, NULL for the other kinds; params_bytes its size.  *actor
+ * receives the id.  E_ARG on unknown kinds or parameters out of range,
+ * E_UNSUPPORTED beyond PRUNE_MAX_* limits, E_STATE after finalize. */
+prune_status prune_actor_create(prune_graph_t g, int kind, const void *params,
+                                size_t params_bytes, prune_id *actor);
+
+/* Add a port to `actor`: dir PRUNE_IN/OUT, kind PRUNE_SRP/DRP/CPORT, active
+ * token rate atr (> 0), token_bytes (8 for complex64 samples and control
+ * tokens), flags (PRUNE_PORT_PARAM) and halo (extra past samples carried by
+ * a window port, Sec. VII-A DPD windows).  *port receives the id. */
+prune_status prune_port_create(prune_graph_t g, prune_id actor, int dir, int kind,
+                               uint32_t atr, uint32_t token_bytes, uint32_t flags,
+                               uint32_t halo, prune_id *port);
+
+/* Id of branch d (0-based, d < n_banks*Kmax) of a filter bank: the DRP pair
+ * of its DC d, addressable in the control table. */
+prune_status prune_filterbank_branch(prune_graph_t g, prune_id fb, uint32_t d, prune_id *drp);
+
+/* Connect output port src to input port dst with rate fiforate and `delay`
+ * initial tokens (zeros).  *fifo receives the id.  E_CONNECT on wrong
+ * directions or an input that already has its FIFO. */
+prune_status prune_fifo_connect(prune_graph_t g, prune_id src_port, prune_id dst_port,
+                                uint32_t fiforate, uint32_t delay, prune_id *fifo);
+
+/* Control table entry T[ctrl_port][drp] = element (1-based element of the
+ * control value; 0 = not controlled), Sec. III-C. */
+prune_status prune_control_table_set(prune_graph_t g, prune_id ctrl_port, prune_id drp,
+                                     uint32_t element);
+
+/* Validate the graph (Sec. III local rules, rule 4 of Sec. IV, the actor
+ * kinds' rate relations) and size every FIFO by Eq. 2 with constant C.
+ * Allocates library-owned device state (counters, control FIFOs, histories,
+ * taps, work lists).  Errors as listed with the status codes. */
+prune_status prune_graph_finalize(prune_graph_t g, uint32_t C);
+
+/* Bytes of storage FIFO `fifo` needs: B * Gamma_f of Eq. 2. */
+prune_status prune_fifo_required_bytes(prune_graph_t g, prune_id fifo, size_t *bytes);
+
+/* Bind caller-owned device storage (borrowed) to a data FIFO.  Control FIFOs
+ * are library-owned.  E_CAPACITY if bytes < prune_fifo_required_bytes. */
+prune_status prune_fifo_bind_storage(prune_graph_t g, prune_id fifo, void *dev_ptr,
+                                     size_t bytes);
+
+/* Device address of the first slot of the k-th next write of `fifo` (for
+ * writing frames in place, the fifoWriteStart window of Sec. VI). */
+prune_status prune_fifo_write_window(prune_graph_t g, prune_id fifo, uint32_t k,
+                                     void **dev_ptr);
+
+/* Copy n_complex complex64 taps from device pointer dev_taps, laid out
+ * [n_banks][Kmax][Lmax] (Lmax = largest L; entries beyond a bank's L
+ * ignored), into the filter bank's library-owned tap buffer. */
+prune_status prune_filterbank_set_taps(prune_graph_t g, prune_id fb, const void *dev_taps,
+                                       size_t n_complex, prune_stream_t stream);
+
+/* Zero the stream history of a stateful filter bank or a switch. */
+prune_status prune_actor_reset_history(prune_graph_t g, prune_id actor, prune_stream_t stream);
+
+/* ---- external input / output -------------------------------------------- */
+
+/* Queue n_frames firings of source `src`.  host_counts[f] = tokens of frame
+ * f (equal to atr for an SRP, 1..atr for a PRUNE_PORT_PARAM port).
+ * dev_samples: device pointer to the frames back to back (copied into the
+ * FIFO when the source fires; must stay valid until then), or NULL when the
+ * caller has already written frame f at prune_fifo_write_window(f). */
+prune_status prune_source_push(prune_graph_t g, prune_id src, const void *dev_samples,
+                               const uint32_t *host_counts, uint32_t n_frames);
+
+/* Queue n_frames firings of configuration actor `cfg` with host side-info. */
+prune_status prune_config_push(prune_graph_t g, prune_id cfg, const prune_side_info *host_side,
+                               uint32_t n_frames, prune_stream_t stream);
+
+/* Optional: every firing of sink `snk` copies its tokens to dev_out at the
+ * running token offset (cap_tokens tokens available).  Without a bound
+ * output the tokens stay in the FIFO storage. */
+prune_status prune_sink_bind_output(prune_graph_t g, prune_id snk, void *dev_out,
+                                    uint64_t cap_tokens);
+
+/* ---- execution (Sec. VI-A actor functions, Sec. VI-C concurrency) -------- */
+
+/* Fire the graph.  PER_FIRING: round-robin sweeps over actors in creation
+ * order, each fireable actor firing at most once per sweep, until nothing
+ * can fire or max_firings (0 = unlimited) firings were issued.  BATCHED /
+ * BATCHED_GRAPH: graph iterations (one firing of every actor that is active
+ * in the iteration) in batches as large as the pending input, the FIFO
+ * capacities and max_firings (read as a cap on iterations per batch, 0 =
+ * none) allow.  *fired (may be NULL) receives firings (PER_FIRING) or
+ * iterations (BATCHED).  E_DEADLOCK if nothing can fire while input is
+ * pending; E_UNSUPPORTED for batched mode on graphs with delays or cycles. */
+prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings,
+                              prune_stream_t stream, uint64_t *fired);
+
+/* Wait for `stream` and check the device error word (rates beyond atr,
+ * control values beyond their size, block counts that differ from the
+ * firing's rate).  Returns the first device-detected error. */
+prune_status prune_graph_sync(prune_graph_t g, prune_stream_t stream);
+
+/* Counters of a FIFO (synchronises the device). */
+prune_status prune_fifo_get_stats(prune_graph_t g, prune_id fifo, prune_fifo_stats *out);
+
+/* Per-branch counters of a filter bank: active firings and tokens of branch
+ * d for d < n (synchronises). */
+prune_status prune_filterbank_branch_stats(prune_graph_t g, prune_id fb, uint64_t *firings,
+                                           uint64_t *tokens, uint32_t n);
+
+/* Firings of an actor so far (host count). */
+prune_status prune_actor_firings(prune_graph_t g, prune_id actor, uint64_t *firings);
+
+/* Start recording per-firing trace records into a library-owned device
+ * buffer of max_records entries (0 disables tracing and frees it). */
+prune_status prune_trace_enable(prune_graph_t g, size_t max_records);
+
+/* Copy the trace to host_buf (capacity `bytes`); *used receives the bytes
+ * written.  E_CAPACITY if the device buffer overflowed. Synchronises. */
+prune_status prune_trace_fetch(prune_graph_t g, void *host_buf, size_t bytes, size_t *used);
+
+/* ---- direct filter-bank operations (same kernels as the graph path) ------ */
+
+/* A batch of frames cut from S streams of N samples each.
+ * frames: device array of n_frames prune_fb_frame, grouped by stream and in
+ * stream order inside a stream; the frames of a stream tile [0, N) of it.
+ * The Lmax-1 samples before t = 0 of every stream are zero. */
+typedef struct {
+  uint32_t n_streams;         /* S                                         */
+  uint32_t n_frames;
+  uint64_t stream_len;        /* N                                         */
+  uint32_t n_banks, Kmax;
+  uint32_t L[PRUNE_MAX_BANKS];
+  uint32_t max_frame_len;     /* largest n of any frame                    */
+  uint32_t reserved;
+} prune_fb_desc;
+
+typedef struct {
+  uint32_t stream;  /* which stream and which tap set                      */
+  uint32_t t0;      /* first sample of the frame within its stream         */
+  uint32_t n;       /* samples                                             */
+  uint32_t mask;    /* bit d: branch d active                              */
+  uint32_t route;   /* 0: filter bank, 1: passthrough (y = x)              */
+  uint32_t pad[3];
+} prune_fb_frame;
+
+/* y = filter bank of x (the forward of the merged DPG over whole streams,
+ * including passthrough-routed frames).  x, y: device [S][N] complex64;
+ * taps: device [S][n_banks][Kmax][Lmax] complex64; frames: device array.
+ * E_UNSUPPORTED beyond the limits, E_ARG on inconsistent descriptors. */
+prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const void *taps,
+                              const void *frames, void *y, prune_stream_t stream);
+
+/* Bytes of device workspace prune_fb_backward needs for `desc`. */
+prune_status prune_fb_workspace_bytes(const prune_fb_desc *desc, size_t *bytes);
+
+/* Adjoint of prune_fb_forward for a real loss (grad = dL/dRe + i dL/dIm):
+ * gx [S][N] and gtaps [S][n_banks][Kmax][Lmax] (entries beyond a bank's L
+ * are written as zero) from the cotangent gy [S][N].  The |x|^p basis is
+ * recomputed, not stored.  workspace: device buffer of at least
+ * prune_fb_workspace_bytes bytes (tile partials and halo gradients). */
+prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const void *taps,
+                               const void *frames, const void *gy, void *gx, void *gtaps,
+                               void *workspace, size_t workspace_bytes, prune_stream_t stream);
+
+/* ---- tuning and diagnostics --------------------------------------------- */
+
+/* Forward kernel variant: 0 = automatic (autotuned, cached), otherwise a
+ * fixed variant index (see prune_fb_variant_name). */
+prune_status prune_set_fb_variant(int variant);
+const char *prune_fb_variant_name(int variant);
+int prune_fb_variant_count(void);
+
+/* Run the autotuner now for the given shape class (taps L, branches K,
+ * frame length n) and report the chosen variant.  Uses the device's null
+ * stream; results are cached per process and in the file named by the
+ * PRUNE_AUTOTUNE_CACHE environment variable when set. */
+prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant);
+
+/* Device-side timing of the filter-bank kernel launches of the last
+ * prune_graph_fire / prune_fb_forward call on this thread (milliseconds,
+ * measured with HIP events on the launch stream when timing is on). */
+prune_status prune_timing_enable(int on);
+prune_status prune_last_fb_kernel_ms(float *ms, uint32_t *launches);
+
+/* ---- host evaluation of the integer rules -------------------------------- */
+/* The kernels' integer rules compiled for the host from the same source:
+ * Eq. 2 capacity (tokens), the first slots of writes and reads 0..n-1 of a
+ * FIFO with rate r, delay Q and constant C (Fig. 6 access pattern), and the
+ * configuration actor's control token for one side-information record.
+ * E_DELAY for delays Eq. 2's buffer cannot hold. */
+prune_status prune_rule_capacity(uint32_t r, uint32_t Q, uint32_t C, uint64_t *tokens);
+prune_status prune_rule_slots(uint32_t r, uint32_t Q, uint32_t C, uint32_t n,
+                              uint64_t *write_slots, uint64_t *read_slots);
+prune_status prune_rule_config_token(uint32_t mode, uint32_t Kmax, const prune_side_info *side,
+                                     prune_ctrl_token *out);
+
+const char *prune_status_string(prune_status s);
+const char *prune_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRUNE_H */

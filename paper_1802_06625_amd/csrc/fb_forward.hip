@@ -1,0 +1,209 @@
+// Filter-bank forward kernels (the fused basis-generation + FIR + branch-sum
+// actor of the DPD application, Sec. VII-A; the DPG of poly, FIR_b and add
+// merged into one firing as in the actor merging of Sec. VII-A's DNN case).
+//
+// For one firing with branch mask m over banks of Kmax branches:
+//   y[n] = sum_{d in m} sum_{l < L_d} h_d[l] |x[n-l]|^{p_d} x[n-l],  p_d = d mod Kmax
+// Within one bank all branches share L, so the branch sum is rewritten per
+// (n, l) as a polynomial in r = |x[n-l]| evaluated by Horner's rule:
+//   y[n] = sum_l x[n-l] * P_l(r[n-l]),  P_l(r) = sum_{b active} h_b[l] r^{b-1}
+// which costs 2(KH-1)+4 fp32 FMAs per (n, l) instead of 4 KH (KH = highest
+// active branch + 1 of the bank; inactive lower branches get zero
+// coefficients).  The arithmetic is fp32 with FMA contraction; r is the
+// correctly rounded sqrtf(re^2 + im^2).
+//
+// Data layout: frames are complex64 (float2) blocks in HBM.  A work item is
+// one tile of T = J*WG consecutive outputs of one frame.  The tile's input
+// window [n0 - (Lpad-1), n0 + T) is staged in LDS as float4 {re, im, r, 0}
+// with one pad float4 per 8 (lane t reads at stride 9 float4, which maps 16
+// lanes onto 64 distinct banks).  Window positions before the frame come from
+// the frame's halo (the stream's past samples), positions after the frame
+// are zero.  Each lane computes J consecutive outputs from a register window
+// of 2J-1 samples per chunk of J taps; the tap coefficients of the chunk are
+// LDS broadcasts.
+#include "prune_internal.h"
+
+namespace prune {
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+
+template <int KH, int J>
+__device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
+                                            const float2 *__restrict__ coef, int Lpad,
+                                            int t, float *accr, float *acci) {
+  const int nchunks = Lpad / J;
+  for (int c = 0; c < nchunks; ++c) {
+    const int base = t * J + (Lpad - c * J - J);
+    float xr[2 * J - 1], xi[2 * J - 1], rr[2 * J - 1];
+#pragma unroll
+    for (int w = 0; w < 2 * J - 1; ++w) {
+      const float4 v = win[pidx(base + w)];
+      xr[w] = v.x;
+      xi[w] = v.y;
+      rr[w] = v.z;
+    }
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      const int l = c * J + i;
+      float2 cf[KH];
+#pragma unroll
+      for (int b = 0; b < KH; ++b) cf[b] = coef[b * Lpad + l];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int w = j - i + J - 1;
+        float ar = cf[KH - 1].x, ai = cf[KH - 1].y;
+#pragma unroll
+        for (int b = KH - 2; b >= 0; --b) {
+          ar = fmaf(ar, rr[w], cf[b].x);
+          ai = fmaf(ai, rr[w], cf[b].y);
+        }
+        accr[j] = fmaf(xr[w], ar, accr[j]);
+        accr[j] = fmaf(-xi[w], ai, accr[j]);
+        acci[j] = fmaf(xr[w], ai, acci[j]);
+        acci[j] = fmaf(xi[w], ar, acci[j]);
+      }
+    }
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void horner_dispatch(int KH, const float4 *win, const float2 *coef,
+                                                int Lpad, int t, float *accr, float *acci) {
+  switch (KH) {
+    case 1: horner_pass<1, J>(win, coef, Lpad, t, accr, acci); break;
+    case 2: horner_pass<2, J>(win, coef, Lpad, t, accr, acci); break;
+    case 3: horner_pass<3, J>(win, coef, Lpad, t, accr, acci); break;
+    case 4: horner_pass<4, J>(win, coef, Lpad, t, accr, acci); break;
+    case 5: horner_pass<5, J>(win, coef, Lpad, t, accr, acci); break;
+    case 6: horner_pass<6, J>(win, coef, Lpad, t, accr, acci); break;
+    case 7: horner_pass<7, J>(win, coef, Lpad, t, accr, acci); break;
+    case 8: horner_pass<8, J>(win, coef, Lpad, t, accr, acci); break;
+    case 9: horner_pass<9, J>(win, coef, Lpad, t, accr, acci); break;
+    default: horner_pass<10, J>(win, coef, Lpad, t, accr, acci); break;
+  }
+}
+
+constexpr int kMaxKH = 10;
+
+// Persistent forward kernel: workgroups take tiles from the item list with an
+// atomic ticket until the list is exhausted.  *ticket must be zero at launch
+// (the producer of the item list clears it).
+template <int J, int WG, int WAVES>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES)))
+void k_fb_forward(const FbFrameDesc *__restrict__ frames,
+                                                   const WorkItem *__restrict__ items,
+                                                   const uint32_t *__restrict__ n_items_ptr,
+                                                   unsigned int *__restrict__ ticket) {
+  constexpr int T = J * WG;
+  constexpr int WMAX = T + PRUNE_MAX_L - 1;
+  __shared__ float4 win[WMAX + (WMAX >> 3) + 1];
+  __shared__ float2 coef[kMaxKH * PRUNE_MAX_L];
+  __shared__ uint32_t s_item;
+  const int t = threadIdx.x;
+  const uint32_t n_items = *n_items_ptr;
+
+  for (;;) {
+    if (t == 0) s_item = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    if (it >= n_items) break;
+    const WorkItem wi = items[it];
+    const FbFrameDesc &d = frames[wi.frame];
+    const int n = (int)d.n;
+    const int n0 = (int)wi.tile * T;
+
+    if (d.route) {
+      // passthrough-routed frame: y = x over the tile
+      for (int k = t; k < T; k += WG) {
+        const int p = n0 + k;
+        if (p < n) {
+          const float2 v = d.x[p];
+          for (uint32_t o = 0; o < d.n_y; ++o) d.y[o][p] = v;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+
+    float accr[J], acci[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) accr[j] = acci[j] = 0.f;
+
+    const int Hd = (int)d.Lmax - 1;
+    const uint32_t kfull = d.Kmax >= 32 ? 0xffffffffu : ((1u << d.Kmax) - 1u);
+    for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+      const uint32_t bmask = (d.mask >> (bank * d.Kmax)) & kfull;
+      if (!bmask) continue;
+      const int KH = 32 - __clz(bmask);
+      const int L = (int)d.L[bank];
+      const int Lpad = (L + J - 1) / J * J;
+      __syncthreads();
+      for (int k = t; k < T + Lpad - 1; k += WG) {
+        const int p = n0 - (Lpad - 1) + k;
+        float2 v = make_float2(0.f, 0.f);
+        if (p >= 0) {
+          if (p < n) v = d.x[p];
+        } else if (-p <= (int)d.halo_valid) {
+          v = d.halo[Hd + p];
+        }
+        win[pidx(k)] = make_float4(v.x, v.y, sqrtf(v.x * v.x + v.y * v.y), 0.f);
+      }
+      const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
+      for (int k = t; k < KH * Lpad; k += WG) {
+        const int b = k / Lpad, l = k - b * Lpad;
+        float2 c = make_float2(0.f, 0.f);
+        if (((bmask >> b) & 1u) && l < L) c = tb[(size_t)b * d.Lmax + l];
+        coef[k] = c;
+      }
+      __syncthreads();
+      horner_dispatch<J>(KH, win, coef, Lpad, t, accr, acci);
+    }
+
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int p = n0 + t * J + j;
+      if (p < n) {
+        const float2 v = make_float2(accr[j], acci[j]);
+        for (uint32_t o = 0; o < d.n_y; ++o) d.y[o][p] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- variants
+struct FbVariant {
+  const char *name;
+  int J, WG;
+  void (*launch)(const FbFrameDesc *, const WorkItem *, const uint32_t *, unsigned int *,
+                 uint32_t grid, hipStream_t);
+};
+
+template <int J, int WG, int WAVES>
+static void launch_fwd(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
+                       unsigned int *ticket, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_fb_forward<J, WG, WAVES>), dim3(grid), dim3(WG), 0, s, f, it, n, ticket);
+}
+
+static const FbVariant kVariants[] = {
+    {"valu_horner_J8_WG256_w2", 8, 256, launch_fwd<8, 256, 2>},
+    {"valu_horner_J4_WG256_w3", 4, 256, launch_fwd<4, 256, 3>},
+    {"valu_horner_J8_WG128_w2", 8, 128, launch_fwd<8, 128, 2>},
+    {"valu_horner_J4_WG128_w4", 4, 128, launch_fwd<4, 128, 4>},
+    {"valu_horner_J8_WG256_w1", 8, 256, launch_fwd<8, 256, 1>},
+};
+
+int fb_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+const char *fb_variant_name(int v) {
+  return (v >= 1 && v <= fb_variant_count()) ? kVariants[v - 1].name : "auto";
+}
+int fb_variant_tile(int v) { return kVariants[v - 1].J * kVariants[v - 1].WG; }
+int fb_variant_wg(int v) { return kVariants[v - 1].WG; }
+
+void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,
+                       const uint32_t *n_items, unsigned int *ticket, uint32_t grid,
+                       hipStream_t s) {
+  kVariants[v - 1].launch(frames, items, n_items, ticket, grid, s);
+}
+
+}  // namespace prune

@@ -1,0 +1,172 @@
+// Internal definitions of libprune_hip shared by the host runtime and the
+// HIP kernels: device-resident FIFO/actor/port tables, per-firing records,
+// filter-bank frame descriptors, and the integer rules of the model of
+// computation written once as __host__ __device__ functions (Eq. 2 capacity,
+// the Fig. 6 slot rule, Eq. 1 decoding, the configuration actor's mapping).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "prune.h"
+
+namespace prune {
+
+constexpr int kMaxPorts = 8;          // ports per actor, control port included
+constexpr int kMaxFanout = 4;         // FIFOs per output port (broadcast)
+constexpr int kMaxIO = 8;             // data FIFO accesses per firing
+constexpr uint32_t kNone = 0xffffffffu;
+
+// Device error word bits (reported by prune_graph_sync).
+enum : uint32_t {
+  kErrToken = 1u,      // control value beyond its declared size
+  kErrRate = 2u,       // rate parameter outside 1..atr
+  kErrCount = 4u,      // block count differs from the firing's rate
+  kErrTrace = 8u,      // trace buffer overflow
+};
+
+// ---------------------------------------------------------------- Eq. 2
+__host__ __device__ inline uint64_t fifo_capacity(uint32_t r, uint32_t Q, uint32_t C) {
+  return (Q % r) ? (uint64_t)r * C + Q
+                 : ((uint64_t)r * C > Q ? (uint64_t)r * C : (uint64_t)Q);
+}
+
+// ---------------------------------------------------------------- Fig. 6 rule
+// Aligned (Q mod r == 0): ring of max(rC, Q) slots in blocks of r, Q/r blocks
+// prefilled; write j -> block (Q/r + j) mod blocks, read i -> block i mod blocks.
+// Unaligned: ring of rC slots plus a Q-slot overflow area; write j at
+// Q + (j mod C) r (copied back to slot 0 when it runs past rC-1), read i at
+// (i mod C) r.
+__host__ __device__ inline uint64_t fifo_write_slot(uint32_t r, uint32_t Q, uint32_t C,
+                                                     uint64_t j) {
+  if (Q % r == 0) {
+    uint64_t blocks = fifo_capacity(r, Q, C) / r;
+    return ((Q / r + j) % blocks) * r;
+  }
+  return Q + (j % C) * (uint64_t)r;
+}
+
+__host__ __device__ inline uint64_t fifo_read_slot(uint32_t r, uint32_t Q, uint32_t C,
+                                                    uint64_t i) {
+  if (Q % r == 0) {
+    uint64_t blocks = fifo_capacity(r, Q, C) / r;
+    return (i % blocks) * r;
+  }
+  return (i % C) * (uint64_t)r;
+}
+
+// Blocking rules in terms of blocks in flight (writes - reads).
+__host__ __device__ inline bool fifo_can_write(uint32_t r, uint32_t Q, uint32_t C,
+                                               int64_t inflight) {
+  if (Q % r == 0) return (int64_t)(Q / r) + inflight < (int64_t)(fifo_capacity(r, Q, C) / r);
+  return (inflight + 1) * (int64_t)r <= (int64_t)r * C - (int64_t)Q;
+}
+
+__host__ __device__ inline bool fifo_can_read(uint32_t r, uint32_t Q, uint32_t C,
+                                              int64_t inflight) {
+  if (Q % r == 0) return (int64_t)(Q / r) + inflight > 0;
+  return (int64_t)Q + inflight * (int64_t)r >= (int64_t)r;
+}
+
+// ---------------------------------------------------------------- Eq. 1
+// tokrate(p, phi) = BTOI(v_phi[T[j][p]]) * atr(p): the element's bit.
+__host__ __device__ inline uint32_t decode_bit(uint32_t mask, uint32_t element) {
+  return element ? (mask >> (element - 1)) & 1u : 0u;
+}
+
+// Configuration actor mapping: external side-information -> control token.
+__host__ __device__ inline prune_ctrl_token config_map(uint32_t mode, uint32_t Kmax,
+                                                       prune_side_info s) {
+  prune_ctrl_token t;
+  if (mode == PRUNE_CONFIG_ROUTE) {
+    t.mask = s.route < 32 ? (1u << s.route) : 0u;
+  } else {
+    uint32_t K = s.K > 31 ? 31 : s.K;
+    uint32_t m = K ? ((K >= 32) ? 0xffffffffu : ((1u << K) - 1u)) : 0u;
+    uint32_t sh = s.bank * Kmax;
+    t.mask = sh < 32 ? (m << sh) : 0u;
+  }
+  t.rate = s.n;
+  return t;
+}
+
+// ---------------------------------------------------------------- device tables
+struct FifoDev {
+  char *base;              // storage: borrowed data FIFO or library-owned control FIFO
+  uint32_t *counts;        // per-block token counts (blocks of r slots)
+  uint32_t r, Q, C, blocks;
+  uint32_t token_bytes, param, halo, aligned;
+  uint64_t writes, reads, tokens_written, tokens_read, max_occ, pad;
+};
+
+struct PortDev {
+  uint32_t actor, dir, kind, atr;
+  uint32_t param, halo, element;   // element: control-table entry of a DRP
+  uint32_t n_fifos;
+  uint32_t fifo[kMaxFanout];
+};
+
+struct ActorDev {
+  uint32_t kind, n_ports, cport_fifo, n_elements;  // cport_fifo = kNone if static
+  uint32_t port[kMaxPorts];                        // PortDev indices (cport excluded)
+  uint32_t first_in;                               // PortDev index of the first data input
+  uint32_t cfg_mode, cfg_Kmax;                     // CONFIG
+  uint32_t fb;                                     // FbParamsDev index for FILTERBANK
+  uint32_t fixed_mask;                             // static filter bank
+  uint32_t hist_len;                               // stream history kept by the actor
+  float2 *history;                                 // [hist_len] library-owned
+  uint64_t firings;                                // device firing counter
+  void *queue;                                     // SOURCE: SrcIn ring; CONFIG: side-info ring
+  uint64_t q_head, q_cap;                          // next entry to consume, ring size
+  float2 *sink_out;                                // SINK: optional bound output
+  uint64_t sink_pos, sink_cap;
+};
+
+struct FbParamsDev {
+  uint32_t n_banks, Kmax, Lmax, windowed;
+  uint32_t L[PRUNE_MAX_BANKS];
+  float2 *taps;           // [n_banks][Kmax][Lmax]
+  uint64_t *branch_firings;  // [n_banks*Kmax]
+  uint64_t *branch_tokens;
+  uint32_t elem[PRUNE_MAX_BRANCHES];  // control-table element of each branch DRP
+};
+
+// One firing's resolved data accesses (output of the bookkeeping step).
+struct IoRec {
+  char *ptr;               // first slot of the access
+  uint32_t count, fifo;
+};
+
+constexpr int kMaxIn = 4;   // data inputs per actor
+
+struct FiringRec {
+  uint32_t fired, firing, mask, rate;
+  uint32_t bitmap, n_io, pad0, pad1;
+  IoRec in[kMaxIn];        // data inputs in port order
+  IoRec out[kMaxIO];       // every (output port, fifo) access in port order
+  uint32_t out_port[kMaxIO];
+};
+
+// Filter-bank firing descriptor consumed by the forward kernels.
+struct FbFrameDesc {
+  const float2 *x;         // sample 0 of the frame
+  const float2 *halo;      // sample -Hd (Hd = Lmax-1); halo[k] = sample k - Hd
+  float2 *y[kMaxFanout];   // outputs (broadcast)
+  const float2 *taps;      // [n_banks][Kmax][Lmax]
+  uint32_t n, mask, halo_valid, n_y;
+  uint32_t n_banks, Kmax, Lmax, route;  // route 1: passthrough copy
+  uint32_t L[PRUNE_MAX_BANKS];
+};
+
+struct WorkItem {
+  uint32_t frame, tile;
+};
+
+// Trace record as in prune.h.
+struct TraceBuf {
+  prune_trace_record *rec;
+  uint64_t cap;
+  unsigned long long *count;
+};
+
+}  // namespace prune

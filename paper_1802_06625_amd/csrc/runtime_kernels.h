@@ -1,0 +1,79 @@
+// Kernel-side argument blocks and launchers shared by the host runtime and
+// the kernel translation units.
+#pragma once
+
+#include "prune_internal.h"
+
+namespace prune {
+
+struct SrcIn {             // one queued source frame
+  uint32_t count, pad;
+  const void *ptr;         // copy-in source, or null when written in place
+};
+
+struct CopyItem {          // dst = halo (halo_count samples), then sum of sources
+  const float2 *src[kMaxIn];
+  float2 *dst;
+  const float2 *halo;
+  uint32_t n_src, halo_count, count, pad;
+};
+
+struct GatherReq {         // fill dst[0..H) with the H stream samples before firing i
+  uint32_t actor, i;
+  float2 *dst;
+};
+
+struct CtrlArgs {
+  FifoDev *fifos;
+  PortDev *ports;
+  ActorDev *actors;
+  FbParamsDev *fbs;
+  const uint32_t *comp_off;      // [n_comp + 1]
+  const uint32_t *comp_actors;   // actors of each component in topological order
+  uint32_t B, Bcap, tile, clear_n;
+  uint32_t per_firing, pad_;
+  FiringRec *recs;               // [n_actors][Bcap]
+  uint32_t *wrote;               // [n_fifos][Bcap] tokens written per iteration
+  FbFrameDesc *fb_desc;
+  const uint32_t *desc_off;      // per actor
+  WorkItem *fb_items;
+  const uint32_t *fb_item_off;   // per level
+  uint32_t *fb_count;            // per level
+  CopyItem *copy_items;
+  const uint32_t *copy_item_off; // per level
+  uint32_t *copy_count;          // per level
+  const uint32_t *level_of;      // per actor
+  float2 *halo_scratch;
+  const uint32_t *halo_off;      // per actor
+  GatherReq *gather_items;
+  const uint32_t *gather_off;    // per level
+  uint32_t *gather_count;        // per level
+  uint32_t *err;
+  uint32_t *clear_ptr;           // zeroed by block 0 first when clear_n > 0 (single block)
+  TraceBuf trace;
+};
+
+void launch_control(const CtrlArgs &c, uint32_t n_comp, hipStream_t s);
+void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x,
+                 uint32_t max_total, hipStream_t s);
+void launch_post(const CtrlArgs &c, const uint32_t *actors, uint32_t n, hipStream_t s);
+void launch_gather(const CtrlArgs &c, uint32_t level, uint32_t grid, hipStream_t s);
+void launch_clear(uint32_t *p, uint32_t n, hipStream_t s);
+
+int fb_variant_count();
+const char *fb_variant_name(int v);
+int fb_variant_tile(int v);
+int fb_variant_wg(int v);
+void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,
+                       const uint32_t *n_items, unsigned int *ticket, uint32_t grid,
+                       hipStream_t s);
+
+// Direct-op helpers.
+void launch_direct_prep(const prune_fb_desc &d, const float2 *x, const float2 *taps,
+                        const prune_fb_frame *frames, float2 *y, uint32_t tile,
+                        FbFrameDesc *desc, WorkItem *items, uint32_t *n_items,
+                        unsigned int *ticket, uint32_t *err, hipStream_t s);
+int choose_variant(uint32_t L, uint32_t K, uint32_t n);
+int forced_variant();
+
+}  // namespace prune

@@ -1,0 +1,112 @@
+"""Direct filter-bank operations over whole streams and their autograd
+Function.  Marshalling only: prune_fb_forward / prune_fb_backward run the HIP
+kernels; torch supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import call
+
+
+def make_desc(n_streams, stream_len, Kmax, bank_L, n_frames, max_frame_len):
+    d = L.FbDesc()
+    d.n_streams = n_streams
+    d.n_frames = n_frames
+    d.stream_len = stream_len
+    d.n_banks = len(bank_L)
+    d.Kmax = Kmax
+    for i, v in enumerate(bank_L):
+        d.L[i] = int(v)
+    d.max_frame_len = int(max_frame_len)
+    return d
+
+
+def frame_table(frames, device="cuda"):
+    """frames: array [F, 5] of (stream, t0, n, mask, route) -> device table of
+    prune_fb_frame records (8 x uint32)."""
+    fr = np.zeros((len(frames), 8), dtype=np.uint32)
+    fr[:, :5] = np.asarray(frames, dtype=np.int64).astype(np.uint32)
+    return torch.from_numpy(fr).to(device)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def fb_forward(x, taps, frames_dev, Kmax, bank_L, max_frame_len):
+    """x: complex64 [S, N] (cuda); taps: complex64 [S, n_banks, Kmax, Lmax];
+    frames_dev: frame_table(...).  Returns y [S, N]."""
+    S, N = x.shape
+    x = x.contiguous()
+    taps = taps.contiguous()
+    y = torch.empty_like(x)
+    d = make_desc(S, N, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
+    call("prune_fb_forward", C.byref(d), C.c_void_p(x.data_ptr()), C.c_void_p(taps.data_ptr()),
+         C.c_void_p(frames_dev.data_ptr()), C.c_void_p(y.data_ptr()), _stream())
+    return y
+
+
+def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len):
+    S, N = x.shape
+    x = x.contiguous()
+    taps = taps.contiguous()
+    gy = gy.contiguous()
+    d = make_desc(S, N, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
+    ws = C.c_size_t()
+    call("prune_fb_workspace_bytes", C.byref(d), C.byref(ws))
+    work = torch.empty(max(1, ws.value), dtype=torch.uint8, device=x.device)
+    gx = torch.empty_like(x)
+    gt = torch.empty_like(taps)
+    call("prune_fb_backward", C.byref(d), C.c_void_p(x.data_ptr()), C.c_void_p(taps.data_ptr()),
+         C.c_void_p(frames_dev.data_ptr()), C.c_void_p(gy.data_ptr()), C.c_void_p(gx.data_ptr()),
+         C.c_void_p(gt.data_ptr()), C.c_void_p(work.data_ptr()), ws.value, _stream())
+    return gx, gt
+
+
+class FilterBankFn(torch.autograd.Function):
+    """y = filter bank(x; taps) over whole streams; gradients w.r.t. x and taps
+    come from the hand-written adjoint kernels (the |x|^p basis is recomputed
+    in the backward, not stored)."""
+
+    @staticmethod
+    def forward(ctx, x, taps, frames_dev, Kmax, bank_L, max_frame_len):
+        ctx.save_for_backward(x, taps, frames_dev)
+        ctx.cfg = (Kmax, tuple(bank_L), max_frame_len)
+        return fb_forward(x, taps, frames_dev, Kmax, bank_L, max_frame_len)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, taps, frames_dev = ctx.saved_tensors
+        Kmax, bank_L, mfl = ctx.cfg
+        gx, gt = fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, mfl)
+        return (gx if ctx.needs_input_grad[0] else None,
+                gt if ctx.needs_input_grad[1] else None, None, None, None, None)
+
+
+def filter_bank(x, taps, frames_dev, Kmax, bank_L, max_frame_len):
+    return FilterBankFn.apply(x, taps, frames_dev, Kmax, bank_L, max_frame_len)
+
+
+def set_variant(v):
+    call("prune_set_fb_variant", int(v))
+
+
+def variant_names():
+    n = L.lib().prune_fb_variant_count()
+    return [L.lib().prune_fb_variant_name(v).decode() for v in range(1, n + 1)]
+
+
+def timing_enable(on=True):
+    call("prune_timing_enable", int(on))
+
+
+def last_fb_kernel_ms():
+    ms = C.c_float()
+    n = C.c_uint32()
+    call("prune_last_fb_kernel_ms", C.byref(ms), C.byref(n))
+    return ms.value, n.value

@@ -1,0 +1,165 @@
+"""Host-side checks of libprune_hip (no GPU needed): the library loads and
+exports every entry point of include/prune.h, its integer rules equal the
+oracle's, and host-only graphs validate like the oracle's graphs."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1802_06625_amd import _lib as L
+from paper_1802_06625_amd.graph import Graph
+from oracle import moc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "prune.h")).read()
+    return sorted(set(re.findall(r"\b(prune_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 35
+    for n in names:
+        assert hasattr(lib, n), n
+    assert {s[0] for s in L.SIGNATURES} == set(names)
+
+
+@pytest.mark.parametrize("r,Q,C", [(4, 1, 3), (4, 0, 3), (4, 8, 3), (4, 16, 3), (3, 2, 2), (5, 3, 3),
+                                   (4, 12, 2), (6, 6, 2), (7, 3, 1), (16384, 0, 4096), (1, 0, 1),
+                                   (65536, 0, 2048), (4, 5, 2), (10, 13, 4)])
+def test_rules_match_oracle(r, Q, C):
+    cap = C.c_uint64() if False else None
+    cap = __import__("ctypes").c_uint64()
+    st = L.lib().prune_rule_capacity(r, Q, C, __import__("ctypes").byref(cap))
+    try:
+        expect = moc.FifoState(0, r, Q, C, np.float64, False).capacity
+    except moc.PruneError as e:
+        assert st == L.E_DELAY and e.code == moc.E_DELAY
+        return
+    assert st == L.OK and cap.value == expect
+    n = 50
+    ws = (__import__("ctypes").c_uint64 * n)()
+    rs = (__import__("ctypes").c_uint64 * n)()
+    assert L.lib().prune_rule_slots(r, Q, C, n, ws, rs) == L.OK
+    assert list(ws) == [moc.fifo_write_slot(r, Q, C, j) for j in range(n)]
+    assert list(rs) == [moc.fifo_read_slot(r, Q, C, i) for i in range(n)]
+
+
+def test_config_token_matches_oracle():
+    import ctypes
+    rng = np.random.default_rng(0)
+    for _ in range(500):
+        mode = int(rng.integers(0, 2))
+        Kmax = int(rng.integers(1, 11))
+        side = L.SideInfo(int(rng.integers(0, Kmax + 1)), int(rng.integers(1, 70000)),
+                          int(rng.integers(0, 3)), int(rng.integers(0, 5)))
+        tok = L.CtrlToken()
+        assert L.lib().prune_rule_config_token(mode, Kmax, ctypes.byref(side), ctypes.byref(tok)) == 0
+        mask, rate = moc.Graph.config_token(dict(mode="route" if mode else "prefix", Kmax=Kmax),
+                                            (side.K, side.n, side.bank, side.route))
+        assert (tok.mask, tok.rate) == (mask, rate)
+
+
+# ---- host-only graph validation -------------------------------------------
+def _plain(g, atr=64, Kmax=4, bank_L=(8,), tweak=None):
+    src = g.actor(L.SOURCE)
+    cfg = g.config(L.CONFIG_PREFIX, Kmax, Kmax * len(bank_L))
+    fb = g.filterbank(Kmax, bank_L)
+    snk = g.actor(L.SINK)
+    ps = g.port(src, L.OUT, L.SRP, atr)
+    pc = g.port(cfg, L.OUT, L.SRP, 1)
+    pcp = g.port(fb, L.IN, L.CPORT, 1)
+    pin = g.port(fb, L.IN, L.SRP, atr if tweak != "rate" else atr + 1)
+    pout = g.port(fb, L.OUT, L.SRP, atr)
+    pk = g.port(snk, L.IN, L.SRP, atr)
+    g.connect(ps, pin, atr)
+    g.connect(pc, pcp, 1)
+    if tweak != "unconnected":
+        g.connect(pout, pk, atr)
+    for d in range(Kmax * len(bank_L)):
+        if tweak == "uncontrolled" and d == 1:
+            continue
+        g.control(pc, g.branch(fb, d), d + 1)
+    return g
+
+
+def test_host_only_plain_graph_validates_and_sizes():
+    g = _plain(Graph(-1))
+    g.finalize(3)
+    assert g.required_bytes(0) == 8 * moc.fifo_capacity(64, 0, 3)
+    assert g.required_bytes(1) == 8 * moc.fifo_capacity(1, 0, 3)
+
+
+@pytest.mark.parametrize("tweak,code", [("rate", L.E_RATE_MISMATCH), ("unconnected", L.E_CONNECT),
+                                        ("uncontrolled", L.E_PORT_KIND)])
+def test_host_only_validation_errors(tweak, code):
+    g = _plain(Graph(-1), tweak=tweak)
+    with pytest.raises(L.PruneError) as e:
+        g.finalize(3)
+    assert e.value.code == code
+
+
+def test_host_only_rule4_and_static_drp():
+    g = Graph(-1)
+    cfg = g.config(L.CONFIG_ROUTE, 1, 2)
+    src = g.actor(L.SOURCE)
+    x = g.actor(L.SELECT)
+    snk = g.actor(L.SINK)
+    pc = g.port(cfg, L.OUT, L.SRP, 1)
+    ps = g.port(src, L.OUT, L.SRP, 4)
+    p1 = g.port(x, L.IN, L.CPORT, 1)
+    p2 = g.port(x, L.IN, L.DRP, 4)
+    p3 = g.port(x, L.OUT, L.DRP, 4)
+    pk = g.port(snk, L.IN, L.SRP, 4)
+    g.connect(pc, p1, 1); g.connect(ps, p2, 4); g.connect(p3, pk, 4)
+    g.control(pc, p2, 1); g.control(pc, p3, 1)
+    with pytest.raises(L.PruneError) as e:
+        g.finalize(3)
+    assert e.value.code in (L.E_RULE4, L.E_ARG)
+    g = Graph(-1)
+    src = g.actor(L.SOURCE); mid = g.actor(L.PASSTHROUGH); snk = g.actor(L.SINK)
+    a = g.port(src, L.OUT, L.SRP, 4); b = g.port(mid, L.IN, L.DRP, 4)
+    c = g.port(mid, L.OUT, L.SRP, 4); d = g.port(snk, L.IN, L.SRP, 4)
+    g.connect(a, b, 4); g.connect(c, d, 4)
+    with pytest.raises(L.PruneError) as e:
+        g.finalize(3)
+    assert e.value.code == L.E_PORT_KIND
+
+
+def test_host_only_delay_rules():
+    for Q, C_, ok in [(1, 3, True), (13, 3, False), (8, 3, True), (1, 1, False)]:
+        g = Graph(-1)
+        src = g.actor(L.SOURCE); mid = g.actor(L.PASSTHROUGH); snk = g.actor(L.SINK)
+        a = g.port(src, L.OUT, L.SRP, 4); b = g.port(mid, L.IN, L.SRP, 4)
+        c = g.port(mid, L.OUT, L.SRP, 4); d = g.port(snk, L.IN, L.SRP, 4)
+        g.connect(a, b, 4, Q); g.connect(c, d, 4)
+        if ok:
+            g.finalize(C_)
+            assert g.required_bytes(0) == 8 * moc.fifo_capacity(4, Q, C_)
+        else:
+            with pytest.raises(L.PruneError) as e:
+                g.finalize(C_)
+            assert e.value.code == L.E_DELAY
+
+
+def test_edit_after_finalize_is_state_error():
+    g = _plain(Graph(-1))
+    g.finalize(2)
+    with pytest.raises(L.PruneError) as e:
+        g.actor(L.SINK)
+    assert e.value.code == L.E_STATE
+
+
+def test_unsupported_shapes():
+    g = Graph(-1)
+    with pytest.raises(L.PruneError) as e:
+        g.filterbank(11, (8,))
+    assert e.value.code == L.E_UNSUPPORTED
+    with pytest.raises(L.PruneError) as e:
+        g.filterbank(4, (65,))
+    assert e.value.code == L.E_UNSUPPORTED

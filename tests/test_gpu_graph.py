@@ -1,0 +1,126 @@
+"""GPU parity of the graph executor against the oracle: integer logs
+(per-FIFO write/read index, slot and count sequences, control decodes,
+counters, branch statistics) bit-exact; sink outputs within 2e-5 relative
+L2 of the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import graphs as og
+from paper_1802_06625_amd import _lib as L
+
+from gpu_util import (TOL, announce, compare_logs, compare_stats, rel_l2, run_plain_device,
+                      run_routed_device)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH])
+@pytest.mark.parametrize("C", [3, 64])
+def test_plain_c1(mode, C):
+    announce(f"plain C1 mode={mode} C={C}")
+    wl = synth.make("C1")
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=C)
+    dev = run_plain_device(wl, C, mode)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+    compare_stats(dev["g"], logs_ref)
+    bf, bt = dev["g"].branch_stats(dev["pg"].fb, wl.Kmax)
+    assert bf == logs_ref["actors"][ids["fb"]]["branch_firings"]
+    assert bt == logs_ref["actors"][ids["fb"]]["branch_tokens"]
+    for a in range(4):
+        assert dev["g"].actor_firings(a) == logs_ref["actors"][a]["firings"]
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH])
+def test_plain_uneven_frames(mode):
+    """Parameterised rates: log-uniform frame lengths, three tap banks."""
+    announce(f"plain C3-scaled mode={mode}")
+    wl = synth.scaled("C3")
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=8)
+    dev = run_plain_device(wl, 8, mode)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+    compare_stats(dev["g"], logs_ref)
+
+
+def test_batched_equals_per_firing_logs():
+    announce("batched vs per-firing logs (C2-scaled)")
+    wl = synth.scaled("C2")
+    a = run_plain_device(wl, 16, L.PER_FIRING)
+    b = run_plain_device(wl, 16, L.BATCHED_GRAPH)
+    assert a["fifos"] == b["fifos"]
+    assert a["ctrl"] == b["ctrl"]
+    assert rel_l2(b["y"], a["y"]) <= 1e-6
+
+
+def test_inplace_source_frames():
+    announce("in-place source frames (C2-scaled)")
+    wl = synth.scaled("C2")
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=wl.n_frames)
+    dev = run_plain_device(wl, wl.n_frames, L.BATCHED, inplace=True)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+
+
+def test_pushes_in_rounds_keep_history():
+    """Frames fired in several calls continue the stream history."""
+    announce("pushes in rounds (C2-scaled)")
+    wl = synth.scaled("C2")
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=4)
+    dev = run_plain_device(wl, 4, L.BATCHED_GRAPH, batches=3)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+
+
+def test_edge_masks_and_short_frames():
+    """mask 0, K=1, K=Kmax and frames shorter than the filter history."""
+    announce("edge masks and short frames")
+    wl = synth.make("C3", n_frames=16, n_max=400)
+    wl.side[0, :, 1] = [1, 5, 40, 31, 2, 300, 17, 64, 1, 3, 250, 9, 33, 1, 100, 7]
+    wl.side[0, :, 0] = [0, 1, 10, 3, 0, 10, 1, 5, 10, 2, 0, 7, 1, 10, 4, 10]
+    wl.side[0, :, 2] = [2, 2, 2, 1, 0, 2, 1, 0, 2, 2, 1, 0, 2, 2, 1, 0]
+    N = int(wl.side[0, :, 1].sum())
+    wl.x = wl.x[:, :N].copy()
+    for mode, C in [(L.PER_FIRING, 3), (L.BATCHED, 16), (L.BATCHED_GRAPH, 5)]:
+        y_ref, logs_ref, _, ids = og.run_plain(wl, C=C, param=True, atr=400)
+        dev = run_plain_device(wl, C, mode, param=True, atr=400)
+        assert rel_l2(dev["y"], y_ref) <= TOL, (mode, C)
+        compare_logs(dev, logs_ref, [ids["fb"]])
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH])
+def test_routed_multistream(mode):
+    announce(f"routed C5-scaled mode={mode}")
+    wl = synth.scaled("C5")
+    y_ref, logs_ref, _, ids = og.run_routed(wl, C=5)
+    dev = run_routed_device(wl, 5, mode)
+    for s in range(wl.n_streams):
+        assert rel_l2(dev["y"][s], y_ref[s]) <= TOL, s
+    ctl = [i["sw"] for i in ids] + [i["sel"] for i in ids]
+    compare_logs(dev, logs_ref, ctl)
+    compare_stats(dev["g"], logs_ref)
+
+
+def test_rate_beyond_atr_is_reported():
+    """A control token whose rate exceeds atr surfaces at sync as E_TOKEN
+    (the firing moves no tokens, so no access leaves the FIFO blocks)."""
+    announce("rate beyond atr")
+    from paper_1802_06625_amd.graph import PlainGraph
+    pg = PlainGraph(4, (8,), 256, 3, param=True)
+    g = pg.g
+    g.set_taps(pg.fb, torch.zeros(32, dtype=torch.complex64, device="cuda"))
+    x = torch.zeros(256, dtype=torch.complex64, device="cuda")
+    g.source_push(pg.src, x, [256])
+    g.config_push(pg.cfg, np.array([[2, 300, 0, 0]], np.uint32))
+    g.fire(L.PER_FIRING)
+    with pytest.raises(L.PruneError) as e:
+        g.sync()
+    assert e.value.code == L.E_TOKEN
