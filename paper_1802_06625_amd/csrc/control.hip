@@ -17,6 +17,8 @@
 //    the data kernels that follow.
 // Static actors fire in an iteration exactly when their first input FIFO was
 // written in that iteration (symmetric rates: one block per firing).
+#include <algorithm>
+
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
@@ -72,17 +74,21 @@ __device__ inline void trace_push(const CtrlArgs &c, uint32_t type, uint32_t a, 
 }
 
 // Tokens moved through port p in a firing with the given rate and activity.
-__device__ inline uint32_t port_count(const CtrlArgs &c, const PortDev &p, const FiringRec &r,
-                                      uint32_t eff_bits) {
-  if (!r.fired) return 0;
-  if (p.kind == PRUNE_DRP && !decode_bit(r.mask, p.element)) return 0;
-  (void)eff_bits;
+__device__ inline uint32_t port_count2(const CtrlArgs &c, const PortDev &p, uint32_t fired,
+                                       uint32_t mask, uint32_t rate) {
+  if (!fired) return 0;
+  if (p.kind == PRUNE_DRP && !decode_bit(mask, p.element)) return 0;
   if (!p.param) return p.atr;
-  if (r.rate < 1u || (uint64_t)r.rate + p.halo > p.atr) {
+  if (rate < 1u || (uint64_t)rate + p.halo > p.atr) {
     atomicOr(c.err, kErrRate);
     return 0;
   }
-  return r.rate + p.halo;
+  return rate + p.halo;
+}
+
+__device__ inline uint32_t port_count(const CtrlArgs &c, const PortDev &p, const FiringRec &r,
+                                      uint32_t) {
+  return port_count2(c, p, r.fired, r.mask, r.rate);
 }
 
 // Past samples of a stateful actor's stream before firing i of this batch:
@@ -440,12 +446,12 @@ constexpr uint32_t kCopyChunk = 4096;
 
 __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items,
                                               const uint32_t *__restrict__ n_items) {
-  const uint32_t it = blockIdx.x;
-  if (it >= *n_items) return;
+  const uint32_t n = *n_items;
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
   const CopyItem ci = items[it];
   const uint32_t total = ci.halo_count + ci.count;
   const uint32_t lo = blockIdx.y * kCopyChunk;
-  if (lo >= total) return;
+  if (lo >= total) continue;
   const uint32_t hi = min(total, lo + kCopyChunk);
   for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
     float2 v;
@@ -461,6 +467,7 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
       }
     }
     ci.dst[k] = v;
+  }
   }
 }
 
@@ -510,7 +517,8 @@ void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x
                  uint32_t max_total, hipStream_t s) {
   const uint32_t gy = (max_total + kCopyChunk - 1) / kCopyChunk;
   if (!grid_x || !gy) return;
-  hipLaunchKernelGGL(k_copy, dim3(grid_x, gy), dim3(256), 0, s, items, n_items);
+  const uint32_t gx = std::min<uint32_t>(grid_x, std::max<uint32_t>(1, 4096 / gy));
+  hipLaunchKernelGGL(k_copy, dim3(gx, gy), dim3(256), 0, s, items, n_items);
 }
 
 void launch_post(const CtrlArgs &c, const uint32_t *actors, uint32_t n, hipStream_t s) {
@@ -525,6 +533,505 @@ void launch_gather(const CtrlArgs &c, uint32_t level, uint32_t grid, hipStream_t
 
 void launch_clear(uint32_t *p, uint32_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(256), 0, s, p, n);
+}
+
+}  // namespace prune
+
+// ======================================================================
+// Parallel batch bookkeeping.  The per-firing path above runs one firing
+// per launch; a batch of B iterations is split into three phases so that
+// only the prefix sums run in one workgroup per component:
+//   decode (thread per iteration): firing, control value, rate, the token
+//     count of every FIFO access, tiles / copy items of the firing;
+//   scan   (workgroup per component): exclusive prefix sums of the accesses
+//     that move tokens (their FIFO indices), firing numbers, work-list
+//     offsets, counters, branch statistics;
+//   emit   (thread per iteration): slots from the indices, firing records,
+//     trace, control tokens into control FIFOs, filter-bank descriptors and
+//     tiles, copy items, halo gather requests.
+// Within an iteration a thread walks the component's actors in topological
+// order, so a static actor sees what its producer wrote in that iteration.
+// ======================================================================
+
+namespace prune {
+
+__global__ __launch_bounds__(256) void k_batch_decode(CtrlArgs c, BatchArgs b) {
+  const uint32_t comp = blockIdx.y;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  // per-level counters and work tickets start at zero for the later phases
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    for (uint32_t k = threadIdx.x; k < c.clear_n; k += blockDim.x) c.clear_ptr[k] = 0u;
+    for (uint32_t f = threadIdx.x; f < c.n_fifos; f += blockDim.x) b.s_rsnap[f] = c.fifos[f].tokens_read;
+  }
+  if (i >= c.B) return;
+  const uint32_t Bc = c.Bcap;
+  uint32_t wrote[kMaxCompFifos];
+  uint32_t tmask[kMaxCompFifos], trate[kMaxCompFifos];
+#pragma unroll
+  for (int k = 0; k < kMaxCompFifos; ++k) { wrote[k] = 0; tmask[k] = 0; trate[k] = 0; }
+  for (uint32_t ka = c.comp_off[comp]; ka < c.comp_off[comp + 1]; ++ka) {
+    const uint32_t a = c.comp_actors[ka];
+    const ActorDev &A = c.actors[a];
+    const uint32_t kind = A.kind;
+    uint32_t fired = 1, mask = 0, rate = 0, bitmap = 0;
+    const void *src_ptr = nullptr;
+    if (kind == PRUNE_SOURCE) {
+      const SrcIn sin = ((const SrcIn *)A.queue)[(A.q_head + i) % A.q_cap];
+      rate = sin.count;
+      src_ptr = sin.ptr;
+    } else if (kind == PRUNE_CONFIG) {
+      const prune_side_info side = ((const prune_side_info *)A.queue)[(A.q_head + i) % A.q_cap];
+      const prune_ctrl_token t = config_map(A.cfg_mode, A.cfg_Kmax, side);
+      mask = t.mask; rate = t.rate;
+    } else if (A.cport_fifo != kNone) {
+      // the control token this iteration's configuration firing wrote
+      const uint32_t k2 = c.fifos[A.cport_fifo].pad;   // local slot of the control FIFO
+      mask = tmask[k2]; rate = trate[k2];
+      if (A.n_elements < 32 && (mask >> A.n_elements)) {
+        atomicOr(c.err, kErrToken);
+        mask &= (1u << A.n_elements) - 1u;
+      }
+    } else {
+      const PortDev &p0 = c.ports[A.first_in];
+      const uint32_t w = wrote[c.fifos[p0.fifo[0]].pad];
+      fired = w != 0;
+      rate = w ? w - p0.halo : 0;
+      mask = A.fixed_mask;
+    }
+    const FbParamsDev *fb = kind == PRUNE_FILTERBANK ? &c.fbs[A.fb] : nullptr;
+    if (fb) {
+      if (A.cport_fifo != kNone) {
+        for (uint32_t d = 0; d < fb->n_banks * fb->Kmax; ++d)
+          bitmap |= decode_bit(mask, fb->elem[d]) << d;
+      } else {
+        bitmap = A.fixed_mask;
+      }
+    }
+    uint32_t in0 = 0, n_out = 0, n_act_out = 0;
+    bool first_in = true;
+    for (uint32_t k2 = b.acc_off[a]; k2 < b.acc_off[a + 1]; ++k2) {
+      const AccDev ac = b.acc[k2];
+      const PortDev &p = c.ports[ac.port];
+      const uint32_t cnt = port_count2(c, p, fired, mask, rate);
+      if (p.kind == PRUNE_DRP && cnt && ac.first) bitmap |= 1u << ac.drp;
+      b.s_cnt[(size_t)k2 * Bc + i] = cnt;
+      if (ac.dir == PRUNE_OUT) {
+        wrote[ac.local] = cnt;
+        if (kind == PRUNE_CONFIG) { tmask[ac.local] = mask; trate[ac.local] = rate; }
+        ++n_out;
+        if (cnt) ++n_act_out;
+      } else if (first_in) {
+        in0 = cnt;
+        first_in = false;
+      }
+    }
+    uint32_t aux = 0;
+    if (fired) {
+      if (fb) {
+        const uint32_t n = fb->windowed ? in0 - (fb->Lmax - 1) : in0;
+        aux = in0 ? (n + c.tile - 1) / c.tile : 0;
+      } else if (kind == PRUNE_SWITCH) {
+        aux = n_act_out;
+      } else if (kind == PRUNE_SOURCE) {
+        aux = src_ptr ? n_out : 0;
+      } else if (kind == PRUNE_SINK) {
+        aux = A.sink_out ? 1 : 0;
+      } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
+        aux = n_out;
+      }
+    }
+    const size_t o = (size_t)a * Bc + i;
+    b.s_fired[o] = fired;
+    b.s_mask[o] = mask;
+    b.s_rate[o] = rate;
+    b.s_bitmap[o] = bitmap;
+    b.s_aux[o] = aux;
+    b.s_aux2[o] = (kind == PRUNE_SINK && fired && A.sink_out) ? in0 : 0;
+  }
+}
+
+// Exclusive scan of v[0..B) into out[0..B) (out may alias v) by one
+// workgroup: contiguous segments per thread, a block scan of their sums.
+// Returns the total.
+__device__ uint32_t seg_scan(const uint32_t *v, uint32_t *out, uint32_t B, bool flag,
+                             uint32_t add, uint32_t *sm32) {
+  const uint32_t nt = blockDim.x, tid = threadIdx.x;
+  const uint32_t S = (B + nt - 1) / nt;
+  const uint32_t lo = min(B, tid * S), hi = min(B, lo + S);
+  uint32_t loc = 0;
+  for (uint32_t i = lo; i < hi; ++i) loc += flag ? (v[i] != 0) : v[i];
+  uint32_t tot;
+  const uint32_t pre = block_excl_scan(loc, &tot, sm32);
+  if (out) {
+    uint32_t run = add + pre;
+    for (uint32_t i = lo; i < hi; ++i) {
+      const uint32_t x = flag ? (v[i] != 0) : v[i];
+      out[i] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  return tot;
+}
+
+// Batch scans run one workgroup per actor.  Arrays are staged through LDS in
+// chunks of kScanE * blockDim elements with coalesced loads and stores; each
+// thread scans a contiguous run of kScanE elements of the chunk.
+constexpr uint32_t kScanNT = 256, kScanE = 8;
+
+// out[i] = base + exclusive prefix of (flag ? v != 0 : v); returns the total
+// and adds the sum of the values to *sum.  out may alias v.
+__device__ uint32_t chunk_scan(const uint32_t *v, uint32_t *out, uint32_t B, bool flag,
+                               uint32_t base, uint64_t *sum, uint32_t *sh, uint32_t *sm32,
+                               unsigned long long *sm64) {
+  const uint32_t nt = blockDim.x, tid = threadIdx.x, CH = nt * kScanE;
+  uint32_t carry = 0;
+  uint64_t sv = 0;
+  for (uint32_t c0 = 0; c0 < B; c0 += CH) {
+#pragma unroll
+    for (uint32_t k = 0; k < kScanE; ++k) {
+      const uint32_t idx = c0 + k * nt + tid;
+      sh[k * nt + tid] = idx < B ? v[idx] : 0u;
+    }
+    __syncthreads();
+    uint32_t loc = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanE; ++k) {
+      const uint32_t x = sh[tid * kScanE + k];
+      loc += flag ? (x != 0) : x;
+      sv += x;
+    }
+    uint32_t tot;
+    const uint32_t pre = block_excl_scan(loc, &tot, sm32);
+    uint32_t run = base + carry + pre;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanE; ++k) {
+      const uint32_t x = sh[tid * kScanE + k];
+      sh[tid * kScanE + k] = run;
+      run += flag ? (x != 0) : x;
+    }
+    __syncthreads();
+    if (out) {
+#pragma unroll
+      for (uint32_t k = 0; k < kScanE; ++k) {
+        const uint32_t idx = c0 + k * nt + tid;
+        if (idx < B) out[idx] = sh[k * nt + tid];
+      }
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (sum) *sum += block_sum_u64(sv, sm64);
+  return carry;
+}
+
+__device__ inline unsigned long long wave_sum(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b) {
+  __shared__ uint32_t sh[kScanNT * kScanE];
+  __shared__ uint32_t sm32[32];
+  __shared__ unsigned long long sm64[32];
+  __shared__ unsigned long long s_bf[PRUNE_MAX_BRANCHES], s_bt[PRUNE_MAX_BRANCHES];
+  __shared__ uint32_t s_res;
+  const uint32_t a = blockIdx.x;
+  const uint32_t B = c.B, Bc = c.Bcap, tid = threadIdx.x, nt = blockDim.x;
+  ActorDev &A = c.actors[a];
+  const uint32_t kind = A.kind;
+  const size_t o = (size_t)a * Bc;
+  // sources, configuration actors and dynamic actors fire every iteration
+  const bool always = kind == PRUNE_SOURCE || kind == PRUNE_CONFIG || A.cport_fifo != kNone;
+  uint32_t nf = B;
+  if (always) {
+    for (uint32_t i = tid; i < B; i += nt) b.s_firing[o + i] = i;
+  } else {
+    nf = chunk_scan(b.s_fired + o, b.s_firing + o, B, true, 0, nullptr, sh, sm32, sm64);
+  }
+  if (tid == 0) {
+    b.s_qbase[a] = (kind == PRUNE_SOURCE || kind == PRUNE_CONFIG) ? A.q_head
+                   : (A.cport_fifo != kNone ? c.fifos[A.cport_fifo].reads : 0);
+    b.s_sink[a] = A.sink_pos;
+  }
+  for (uint32_t k2 = b.acc_off[a]; k2 < b.acc_off[a + 1]; ++k2) {
+    const AccDev ac = b.acc[k2];
+    FifoDev &f = c.fifos[ac.fifo];
+    const uint32_t *cnt = b.s_cnt + (size_t)k2 * Bc;
+    uint32_t *pre = b.s_pre + (size_t)k2 * Bc;
+    uint32_t nacc;
+    uint64_t toks = 0;
+    if (always && c.ports[ac.port].kind != PRUNE_DRP) {
+      // an SRP of an actor that fires every iteration is accessed every iteration
+      uint64_t loc = 0;
+      for (uint32_t i = tid; i < B; i += nt) {
+        pre[i] = i;
+        loc += cnt[i];
+      }
+      nacc = B;
+      toks = block_sum_u64(loc, sm64);
+    } else {
+      nacc = chunk_scan(cnt, pre, B, true, 0, &toks, sh, sm32, sm64);
+    }
+    if (tid == 0) {
+      // each FIFO has one writer access and one reader access: no other
+      // workgroup updates these fields
+      if (ac.dir == PRUNE_IN) {
+        b.s_base[k2] = f.reads;
+        f.reads += nacc;
+        f.tokens_read += toks;
+      } else {
+        b.s_base[k2] = f.writes;
+        f.writes += nacc;
+        f.tokens_written += toks;
+        // occupancy with all of this batch's tokens written, before its reads
+        const uint64_t occ = f.Q + f.tokens_written - b.s_rsnap[ac.fifo];
+        if (occ > f.max_occ) f.max_occ = occ;
+      }
+    }
+  }
+  if (tid == 0) {
+    A.firings += nf;
+    if (kind == PRUNE_SOURCE || kind == PRUNE_CONFIG) A.q_head += B;
+    if (A.cport_fifo != kNone) {
+      c.fifos[A.cport_fifo].reads += nf;
+      c.fifos[A.cport_fifo].tokens_read += nf;
+    }
+  }
+  const uint32_t lev = c.level_of[a];
+  if (kind == PRUNE_FILTERBANK || kind == PRUNE_SWITCH || kind == PRUNE_SELECT ||
+      kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK) {
+    const bool fbk = kind == PRUNE_FILTERBANK;
+    // total first, then the region, then the offsets
+    uint32_t loc = 0;
+    for (uint32_t i = tid; i < B; i += nt) loc += b.s_aux[o + i];
+    const uint64_t tot = block_sum_u64(loc, sm64);
+    if (tid == 0) s_res = atomicAdd((fbk ? c.fb_count : c.copy_count) + lev, (uint32_t)tot);
+    __syncthreads();
+    const uint32_t base = (fbk ? c.fb_item_off[lev] : c.copy_item_off[lev]) + s_res;
+    chunk_scan(b.s_aux + o, b.s_auxoff + o, B, false, base, nullptr, sh, sm32, sm64);
+  }
+  if (kind == PRUNE_SINK && A.sink_out) {
+    const uint32_t tot = chunk_scan(b.s_aux2 + o, b.s_aux2 + o, B, false, 0, nullptr, sh, sm32, sm64);
+    if (tid == 0) A.sink_pos += tot;
+  }
+  if (kind == PRUNE_FILTERBANK) {
+    // branch statistics: per-thread counts in registers, wave sums, then
+    // one shared-memory add per wave and branch
+    const FbParamsDev &fb = c.fbs[A.fb];
+    const uint32_t D = fb.n_banks * fb.Kmax;
+    for (uint32_t d = tid; d < D; d += nt) { s_bf[d] = 0; s_bt[d] = 0; }
+    __syncthreads();
+    uint32_t in_acc = b.acc_off[a];
+    while (in_acc < b.acc_off[a + 1] && b.acc[in_acc].dir != PRUNE_IN) ++in_acc;
+    const uint32_t *cin = b.s_cnt + (size_t)in_acc * Bc;
+    const uint32_t H = fb.windowed ? fb.Lmax - 1 : 0;
+    for (uint32_t d0 = 0; d0 < D; d0 += 16) {
+      uint32_t bf[16];
+      unsigned long long bt[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) { bf[k] = 0; bt[k] = 0; }
+      for (uint32_t i = tid; i < B; i += nt) {
+        if (!b.s_fired[o + i]) continue;
+        const uint32_t bm = b.s_bitmap[o + i] >> d0;
+        const uint32_t n = cin[i] ? cin[i] - H : 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const uint32_t on = (bm >> k) & 1u;
+          bf[k] += on;
+          bt[k] += on ? n : 0u;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const unsigned long long wf = wave_sum(bf[k]), wt = wave_sum(bt[k]);
+        if ((tid & 63) == 0 && d0 + k < D) {
+          atomicAdd(&s_bf[d0 + k], wf);
+          atomicAdd(&s_bt[d0 + k], wt);
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < D; d += nt) {
+      fb.branch_firings[d] += s_bf[d];
+      fb.branch_tokens[d] += s_bt[d];
+    }
+  }
+}
+
+// Halo of firing i of a stateful actor from the batch's own records: the
+// stored history for the first firing, the tail of the previous input block
+// when it is long enough, else a gather request filled by k_gather.
+__device__ inline const float2 *batch_halo(const CtrlArgs &c, const BatchArgs &b, uint32_t a,
+                                           uint32_t in_acc, uint32_t i) {
+  const ActorDev &A = c.actors[a];
+  const uint32_t H = A.hist_len;
+  if (i == 0) return A.history;
+  const size_t q = (size_t)in_acc * c.Bcap + (i - 1);
+  const uint32_t cp = b.s_cnt[q];
+  if (cp >= H) {
+    const AccDev ac = b.acc[in_acc];
+    const FifoDev &f = c.fifos[ac.fifo];
+    const uint64_t slot = fifo_read_slot(f.r, f.Q, f.C, b.s_base[in_acc] + b.s_pre[q]);
+    return (const float2 *)(f.base + slot * f.token_bytes) + (cp - H);
+  }
+  float2 *dst = c.halo_scratch + (size_t)c.halo_off[a] + (size_t)i * H;
+  const uint32_t lev = c.level_of[a];
+  const uint32_t k = atomicAdd(c.gather_count + lev, 1u);
+  GatherReq g;
+  g.actor = a; g.i = i; g.dst = dst;
+  c.gather_items[c.gather_off[lev] + k] = g;
+  return dst;
+}
+
+__global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.B) return;
+  const uint32_t Bc = c.Bcap, last = c.B - 1;
+  {
+    const uint32_t a = blockIdx.y;
+    const ActorDev &A = c.actors[a];
+    const uint32_t kind = A.kind;
+    const size_t ab = (size_t)a * Bc, o = ab + i;
+    FiringRec r;
+    r.fired = b.s_fired[o];
+    const uint32_t batch_fired = b.s_firing[ab + last] + b.s_fired[ab + last];
+    r.firing = (uint32_t)(A.firings - batch_fired + b.s_firing[o]);
+    r.mask = b.s_mask[o];
+    r.rate = b.s_rate[o];
+    r.bitmap = b.s_bitmap[o];
+    r.pad0 = r.pad1 = 0;
+    for (int s = 0; s < kMaxIn; ++s) { r.in[s].ptr = nullptr; r.in[s].count = 0; r.in[s].fifo = kNone; }
+    uint32_t n_out = 0, in_acc = kNone;
+    for (uint32_t k2 = b.acc_off[a]; k2 < b.acc_off[a + 1]; ++k2) {
+      const AccDev ac = b.acc[k2];
+      FifoDev &f = c.fifos[ac.fifo];
+      const uint32_t cnt = b.s_cnt[(size_t)k2 * Bc + i];
+      char *ptr = nullptr;
+      if (cnt) {
+        const uint64_t idx = b.s_base[k2] + b.s_pre[(size_t)k2 * Bc + i];
+        const uint64_t slot = ac.dir == PRUNE_IN ? fifo_read_slot(f.r, f.Q, f.C, idx)
+                                                 : fifo_write_slot(f.r, f.Q, f.C, idx);
+        ptr = f.base + slot * f.token_bytes;
+        const uint32_t blk = (uint32_t)(slot / f.r);
+        if (f.param) {
+          // in a batch the read of iteration i takes the block written in
+          // iteration i: compare with the writer's count of that iteration
+          if (ac.dir == PRUNE_OUT) f.counts[blk] = cnt;
+          else if (b.s_cnt[(size_t)b.fifo_wacc[ac.fifo] * Bc + i] != cnt) atomicOr(c.err, kErrCount);
+        }
+        trace_push(c, 0, ac.fifo, ac.dir == PRUNE_IN ? 1u : 0u, r.firing, (uint32_t)idx,
+                   (uint32_t)slot, cnt);
+      }
+      if (ac.dir == PRUNE_IN) {
+        if (in_acc == kNone) in_acc = k2;
+        if (ac.slot < (uint32_t)kMaxIn) {
+          r.in[ac.slot].ptr = ptr; r.in[ac.slot].count = cnt; r.in[ac.slot].fifo = ac.fifo;
+        }
+      } else if (ac.slot < (uint32_t)kMaxIO) {
+        r.out[ac.slot].ptr = ptr; r.out[ac.slot].count = cnt; r.out[ac.slot].fifo = ac.fifo;
+        r.out_port[ac.slot] = ac.port;
+        n_out = max(n_out, ac.slot + 1);
+      }
+    }
+    r.n_io = n_out;
+    if (A.cport_fifo != kNone && r.fired) {
+      const FifoDev &f = c.fifos[A.cport_fifo];
+      const uint64_t idx = b.s_qbase[a] + b.s_firing[o];
+      trace_push(c, 0, A.cport_fifo, 1u, r.firing, (uint32_t)idx,
+                 (uint32_t)fifo_read_slot(f.r, f.Q, f.C, idx), 1u);
+      trace_push(c, 1, a, 0u, r.firing, r.mask, r.rate, r.bitmap);
+    }
+    c.recs[o] = r;
+    if (!r.fired) return;
+
+    if (kind == PRUNE_CONFIG) {
+      prune_ctrl_token t;
+      t.mask = r.mask;
+      t.rate = r.rate;
+      for (uint32_t k = 0; k < n_out; ++k)
+        if (r.out[k].ptr) *(prune_ctrl_token *)r.out[k].ptr = t;
+    } else if (kind == PRUNE_FILTERBANK) {
+      const FbParamsDev &fb = c.fbs[A.fb];
+      const uint32_t H = fb.Lmax - 1;
+      FbFrameDesc d;
+      const char *xin = r.in[0].ptr;
+      const uint32_t cin = r.in[0].count;
+      d.n = cin ? (fb.windowed ? cin - H : cin) : 0;
+      d.x = (const float2 *)xin + (fb.windowed ? H : 0);
+      d.halo = fb.windowed ? (const float2 *)xin : batch_halo(c, b, a, in_acc, i);
+      d.halo_valid = H;
+      d.n_y = 0;
+      for (uint32_t k = 0; k < n_out && k < (uint32_t)kMaxFanout; ++k)
+        if (r.out[k].ptr) d.y[d.n_y++] = (float2 *)r.out[k].ptr;
+      d.taps = fb.taps;
+      d.mask = r.bitmap;
+      d.n_banks = fb.n_banks; d.Kmax = fb.Kmax; d.Lmax = fb.Lmax; d.route = 0;
+      for (int q = 0; q < PRUNE_MAX_BANKS; ++q) d.L[q] = fb.L[q];
+      const uint32_t di = c.desc_off[a] + i;
+      c.fb_desc[di] = d;
+      const uint32_t tiles = b.s_aux[o], base = b.s_auxoff[o];
+      for (uint32_t t = 0; t < tiles; ++t) {
+        WorkItem w;
+        w.frame = di;
+        w.tile = t;
+        c.fb_items[base + t] = w;
+      }
+    } else {
+      uint32_t base = b.s_auxoff[o], n = 0;
+      CopyItem ci;
+      for (int s = 0; s < kMaxIn; ++s) ci.src[s] = nullptr;
+      ci.halo = nullptr; ci.halo_count = 0; ci.pad = 0;
+      if (kind == PRUNE_SWITCH) {
+        const float2 *hp = batch_halo(c, b, a, in_acc, i);
+        for (uint32_t k = 0; k < n_out; ++k) {
+          if (!r.out[k].ptr) continue;
+          const PortDev &p = c.ports[r.out_port[k]];
+          ci.n_src = 1; ci.src[0] = (const float2 *)r.in[0].ptr;
+          ci.dst = (float2 *)r.out[k].ptr;
+          ci.halo = hp + (A.hist_len - p.halo); ci.halo_count = p.halo;
+          ci.count = r.in[0].count;
+          c.copy_items[base + n++] = ci;
+        }
+      } else if (kind == PRUNE_SOURCE) {
+        const SrcIn sin = ((const SrcIn *)A.queue)[(b.s_qbase[a] + i) % A.q_cap];
+        if (sin.ptr)
+          for (uint32_t k = 0; k < n_out; ++k) {
+            ci.n_src = 1; ci.src[0] = (const float2 *)sin.ptr;
+            ci.dst = (float2 *)r.out[k].ptr; ci.count = r.out[k].count;
+            c.copy_items[base + n++] = ci;
+          }
+      } else if (kind == PRUNE_SINK) {
+        if (A.sink_out) {
+          const uint64_t off = b.s_sink[a] + b.s_aux2[o];
+          ci.n_src = 1; ci.src[0] = (const float2 *)r.in[0].ptr; ci.count = r.in[0].count;
+          if (off + ci.count <= A.sink_cap) {
+            ci.dst = A.sink_out + off;
+          } else {
+            ci.dst = nullptr; ci.count = 0; ci.n_src = 0;
+            atomicOr(c.err, kErrCount);
+          }
+          if (ci.dst) c.copy_items[base + n++] = ci;
+          else { ci.dst = A.sink_out; c.copy_items[base + n++] = ci; }
+        }
+      } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
+        for (uint32_t k = 0; k < n_out; ++k) {
+          ci.n_src = 0;
+          for (int s = 0; s < kMaxIn; ++s)
+            if (r.in[s].ptr) ci.src[ci.n_src++] = (const float2 *)r.in[s].ptr;
+          ci.dst = (float2 *)r.out[k].ptr; ci.count = r.out[k].count;
+          c.copy_items[base + n++] = ci;
+        }
+      }
+    }
+  }
+}
+
+void launch_batch(const CtrlArgs &c, const BatchArgs &b, uint32_t n_comp, uint32_t n_actors,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_decode, dim3((c.B + 255) / 256, n_comp), dim3(256), 0, s, c, b);
+  hipLaunchKernelGGL(k_batch_scan, dim3(n_actors), dim3(kScanNT), 0, s, c, b);
+  hipLaunchKernelGGL(k_batch_emit, dim3((c.B + 63) / 64, n_actors), dim3(64), 0, s, c, b);
 }
 
 }  // namespace prune

@@ -1,18 +1,543 @@
-// Adjoint of the filter-bank forward (placeholder until the adjoint kernels land).
+// Adjoint of the filter bank over whole streams (prune_fb_backward).
+//
+// For a real loss with grad = dL/dRe + i dL/dIm, cotangent g = grad_y,
+// p = b-1, r = |x|, and G_b[m] = sum_l conj(h_b[l]) g[m+l] over outputs of
+// frames where branch b is active:
+//   grad_h_b[l] = sum_n g[n] conj(x[n-l]) r[n-l]^p
+//   grad_x[m]   = sum_b (p/2+1) r^p G_b + (p/2) r^(p-2) x^2 conj(G_b)
+//               = S1 + (x^2 / r^2) S2,
+//   S1 = sum_l g[m+l]       Q_l(r),  Q_l(r) = sum_b (p/2+1) conj(h_b[l]) r^p
+//   S2 = sum_l conj(g[m+l]) T_l(r),  T_l(r) = sum_b (p/2)   h_b[l]       r^p
+// Q_l and T_l are evaluated by Horner's rule in r (the |x|^p basis is
+// recomputed, never stored); S2 carries r^p with p >= 1, so the term is zero
+// at r = 0 and x^2/r^2 has magnitude 1.  Passthrough frames pass g through.
+//
+// Kernels (one tile = T consecutive outputs of one frame, as in the forward):
+//  k_bwd_prep   frame descriptors, tile list, per-stream tile ranges;
+//  k_bwd_main   per tile: grad_x at the tile's inputs from the frame's own
+//               outputs, and the tile's grad_h partial (fp32, reduced over
+//               the tile in a fixed order);
+//  k_bwd_halo   per frame: gradient of the Lmax-1 past samples its window
+//               reads (contributions that belong to earlier frames);
+//  k_bwd_fix    adds those halo gradients into the earlier frames' grad_x
+//               (each element written by exactly one thread);
+//  k_bwd_reduce1/2  fixed-order float64 sums of the tile partials per stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "prune.h"
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
-extern "C" {
-prune_status prune_fb_workspace_bytes(const prune_fb_desc *desc, size_t *bytes) {
-  (void)desc;
-  if (bytes) *bytes = 0;
-  return PRUNE_E_UNSUPPORTED;
+namespace prune {
+
+constexpr int kBJ = 4;          // inputs per lane for grad_x
+constexpr int kBWG = 256;
+constexpr int kBT = kBJ * kBWG;  // tile
+constexpr int kRedChunk = 64;    // tiles per first-stage reduction chunk
+constexpr int kRedG = 64;        // chunk groups per stream
+
+struct BwdFrame {
+  const float2 *x;      // sample 0 of the frame (stream pointer + t0)
+  const float2 *g;      // cotangent at sample 0
+  float2 *gx;           // grad_x at sample 0
+  const float2 *taps;   // [n_banks][Kmax][Lmax] of the frame's stream
+  uint32_t n, mask, route, t0;
+  uint32_t stream, pad0, pad1, pad2;
+};
+
+__device__ __forceinline__ int bidx(int i) { return i + (i >> 3); }
+
+__global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2 *x,
+                                                   const float2 *taps, const prune_fb_frame *fr,
+                                                   const float2 *g, float2 *gx, BwdFrame *bf,
+                                                   WorkItem *items, uint32_t *n_items,
+                                                   uint32_t *s_begin, uint32_t *s_end) {
+  __shared__ uint32_t sm[32];
+  __shared__ uint32_t s_carry;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const size_t tstride = (size_t)d.n_banks * d.Kmax * Lmax;
+  for (uint32_t s = tid; s < d.n_streams; s += nt) { s_begin[s] = 0; s_end[s] = 0; }
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < d.n_frames; base += nt) {
+    const uint32_t f = base + tid;
+    uint32_t tiles = 0;
+    prune_fb_frame q;
+    if (f < d.n_frames) {
+      q = fr[f];
+      const bool ok = q.stream < d.n_streams && (uint64_t)q.t0 + q.n <= d.stream_len &&
+                      q.n <= d.max_frame_len;
+      BwdFrame b;
+      const size_t so = (size_t)q.stream * d.stream_len + q.t0;
+      b.x = x + so; b.g = g + so; b.gx = gx + so;
+      b.taps = taps + (size_t)q.stream * tstride;
+      b.n = ok ? q.n : 0; b.mask = q.mask; b.route = q.route; b.t0 = q.t0; b.stream = q.stream;
+      b.pad0 = b.pad1 = b.pad2 = 0;
+      bf[f] = b;
+      tiles = (b.n + kBT - 1) / kBT;
+    }
+    uint32_t v = tiles;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
+    }
+    if (lane == 63) sm[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+      uint32_t w = lane < nw ? sm[lane] : 0u;
+      for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(w, o, 64);
+        if (lane >= o) w += t;
+      }
+      if (lane < nw) sm[lane] = w;
+    }
+    __syncthreads();
+    const uint32_t pre = s_carry + (wid ? sm[wid - 1] : 0u) + v - tiles;
+    if (f < d.n_frames) {
+      for (uint32_t k = 0; k < tiles; ++k) {
+        WorkItem it;
+        it.frame = f;
+        it.tile = k;
+        items[pre + k] = it;
+      }
+      if (q.stream < d.n_streams) {
+        if (f == 0 || fr[f - 1].stream != q.stream) s_begin[q.stream] = pre;
+        if (f + 1 == d.n_frames || fr[f + 1].stream != q.stream) s_end[q.stream] = pre + tiles;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_carry += sm[nw - 1];
+    __syncthreads();
+  }
+  if (tid == 0) *n_items = s_carry;
 }
+
+// grad_x of the J inputs a lane owns for one chunk of J taps.
+template <int KH>
+__device__ __forceinline__ void gx_pass(const float2 *__restrict__ gw, const float2 *__restrict__ cq,
+                                        const float2 *__restrict__ ct, int Lpad, int t,
+                                        const float *rm, float *s1r, float *s1i, float *s2r,
+                                        float *s2i) {
+  for (int c = 0; c < Lpad / kBJ; ++c) {
+    float gr[2 * kBJ - 1], gi[2 * kBJ - 1];
+#pragma unroll
+    for (int w = 0; w < 2 * kBJ - 1; ++w) {
+      const float2 v = gw[bidx(t * kBJ + c * kBJ + w)];
+      gr[w] = v.x;
+      gi[w] = v.y;
+    }
+#pragma unroll
+    for (int i = 0; i < kBJ; ++i) {
+      const int l = c * kBJ + i;
+      float2 q[KH], tt[KH];
+#pragma unroll
+      for (int b = 0; b < KH; ++b) {
+        q[b] = cq[b * Lpad + l];
+        tt[b] = ct[b * Lpad + l];
+      }
+#pragma unroll
+      for (int j = 0; j < kBJ; ++j) {
+        const int w = j + i;
+        float qr = q[KH - 1].x, qi = q[KH - 1].y, tr = tt[KH - 1].x, ti = tt[KH - 1].y;
+#pragma unroll
+        for (int b = KH - 2; b >= 0; --b) {
+          qr = fmaf(qr, rm[j], q[b].x);
+          qi = fmaf(qi, rm[j], q[b].y);
+          tr = fmaf(tr, rm[j], tt[b].x);
+          ti = fmaf(ti, rm[j], tt[b].y);
+        }
+        // S1 += g * Q ; S2 += conj(g) * T
+        s1r[j] = fmaf(gr[w], qr, s1r[j]);
+        s1r[j] = fmaf(-gi[w], qi, s1r[j]);
+        s1i[j] = fmaf(gr[w], qi, s1i[j]);
+        s1i[j] = fmaf(gi[w], qr, s1i[j]);
+        s2r[j] = fmaf(gr[w], tr, s2r[j]);
+        s2r[j] = fmaf(gi[w], ti, s2r[j]);
+        s2i[j] = fmaf(gr[w], ti, s2i[j]);
+        s2i[j] = fmaf(-gi[w], tr, s2i[j]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void gx_dispatch(int KH, const float2 *gw, const float2 *cq,
+                                            const float2 *ct, int Lpad, int t, const float *rm,
+                                            float *a, float *b, float *c, float *d) {
+  switch (KH) {
+    case 1: gx_pass<1>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 2: gx_pass<2>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 3: gx_pass<3>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 4: gx_pass<4>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 5: gx_pass<5>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 6: gx_pass<6>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 7: gx_pass<7>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 8: gx_pass<8>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    case 9: gx_pass<9>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+    default: gx_pass<10>(gw, cq, ct, Lpad, t, rm, a, b, c, d); break;
+  }
+}
+
+// Coefficients of Q_l and T_l for one bank of a frame (zero for inactive branches).
+__device__ inline void load_coefs(const float2 *tb, uint32_t Lmax, uint32_t bmask, int KH, int L,
+                                  int Lpad, float2 *cq, float2 *ct) {
+  for (int k = threadIdx.x; k < KH * Lpad; k += blockDim.x) {
+    const int b = k / Lpad, l = k - b * Lpad;
+    float2 h = make_float2(0.f, 0.f);
+    if (((bmask >> b) & 1u) && l < L) h = tb[(size_t)b * Lmax + l];
+    const float al = 0.5f * (float)b + 1.f, be = 0.5f * (float)b;
+    cq[k] = make_float2(al * h.x, -al * h.y);
+    ct[k] = make_float2(be * h.x, be * h.y);
+  }
+}
+
+__global__ __launch_bounds__(kBWG) void k_bwd_main(prune_fb_desc d, const BwdFrame *__restrict__ bf,
+                                                  const WorkItem *__restrict__ items,
+                                                  const uint32_t *__restrict__ n_items,
+                                                  float2 *__restrict__ partial) {
+  constexpr int WM = kBT + PRUNE_MAX_L - 1;
+  __shared__ float4 xw[WM + (WM >> 3) + 1];   // x window {re, im, r, 0}, positions n0-(Lpad-1) ..
+  __shared__ float2 gw[WM + (WM >> 3) + 1];   // g window, positions n0 .. n0+T+Lpad-2
+  __shared__ float2 cq[10 * PRUNE_MAX_L], ct[10 * PRUNE_MAX_L];
+  __shared__ float2 red[kBWG];                // grad_h chunk partials
+  const int t = threadIdx.x;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const uint32_t D = d.n_banks * d.Kmax;
+  const uint32_t ni = *n_items;
+  for (uint32_t it = blockIdx.x; it < ni; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const BwdFrame F = bf[wi.frame];
+    const int n = (int)F.n, n0 = (int)wi.tile * kBT;
+    float2 *prow = partial + (size_t)it * D * Lmax;
+    if (F.route) {
+      for (int k = t; k < kBT; k += kBWG)
+        if (n0 + k < n) F.gx[n0 + k] = F.g[n0 + k];
+      for (uint32_t k = t; k < D * Lmax; k += kBWG) prow[k] = make_float2(0.f, 0.f);
+      __syncthreads();
+      continue;
+    }
+    float s1r[kBJ], s1i[kBJ], s2r[kBJ], s2i[kBJ], xr[kBJ], xi[kBJ], rm[kBJ];
+#pragma unroll
+    for (int j = 0; j < kBJ; ++j) s1r[j] = s1i[j] = s2r[j] = s2i[j] = xr[j] = xi[j] = rm[j] = 0.f;
+    const uint32_t kfull = (1u << d.Kmax) - 1u;
+    for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+      const uint32_t bmask = (F.mask >> (bank * d.Kmax)) & kfull;
+      float2 *brow = prow + (size_t)bank * d.Kmax * Lmax;
+      if (!bmask) {
+        for (uint32_t k = t; k < d.Kmax * Lmax; k += kBWG) brow[k] = make_float2(0.f, 0.f);
+        continue;
+      }
+      const int KH = 32 - __clz(bmask);
+      const int L = (int)d.L[bank];
+      const int Lpad = (L + kBJ - 1) / kBJ * kBJ;
+      __syncthreads();
+      for (int k = t; k < kBT + Lpad - 1; k += kBWG) {
+        const int p = n0 - (Lpad - 1) + k;   // x window
+        float2 v = make_float2(0.f, 0.f);
+        if (p < n && p >= -(int)F.t0) v = F.x[p];
+        xw[bidx(k)] = make_float4(v.x, v.y, sqrtf(v.x * v.x + v.y * v.y), 0.f);
+        const int q = n0 + k;                // g window (outputs of this frame only)
+        gw[bidx(k)] = q < n ? F.g[q] : make_float2(0.f, 0.f);
+      }
+      load_coefs(F.taps + (size_t)bank * d.Kmax * Lmax, Lmax, bmask, KH, L, Lpad, cq, ct);
+      __syncthreads();
+      // ---- grad_x of inputs n0 + t*J + j
+#pragma unroll
+      for (int j = 0; j < kBJ; ++j) {
+        const float4 v = xw[bidx(t * kBJ + j + Lpad - 1)];
+        xr[j] = v.x; xi[j] = v.y; rm[j] = v.z;
+      }
+      gx_dispatch(KH, gw, cq, ct, Lpad, t, rm, s1r, s1i, s2r, s2i);
+      // ---- grad_h partial of this tile: lane l = t % Lpad, chunk = t / Lpad
+      if (Lpad <= kBWG) {
+        const int nch = kBWG / Lpad, l = t % Lpad, ch = t / Lpad;
+        const int per = (kBT + nch - 1) / nch;
+        float ar[10], ai[10];
+#pragma unroll
+        for (int b = 0; b < 10; ++b) ar[b] = ai[b] = 0.f;
+        if (ch < nch) {
+          const int hi = min(kBT, (ch + 1) * per);
+          for (int k = ch * per; k < hi; ++k) {
+            const float2 gv = gw[bidx(k)];
+            const float4 xv = xw[bidx(k - l + Lpad - 1)];
+            // w = g * conj(x)
+            const float wr = gv.x * xv.x + gv.y * xv.y;
+            const float wi2 = gv.y * xv.x - gv.x * xv.y;
+            float rp = 1.f;
+#pragma unroll
+            for (int b = 0; b < 10; ++b) {
+              if (b < KH) {
+                ar[b] = fmaf(wr, rp, ar[b]);
+                ai[b] = fmaf(wi2, rp, ai[b]);
+                rp *= xv.z;
+              }
+            }
+          }
+        }
+        // fixed-order reduction over the chunks of each (b, l)
+        for (int b = 0; b < KH; ++b) {
+          __syncthreads();
+          if (ch < nch) red[ch * Lpad + l] = make_float2(ar[b], ai[b]);
+          __syncthreads();
+          if (t < Lpad) {
+            float sr = 0.f, si = 0.f;
+            for (int q = 0; q < nch; ++q) {
+              sr += red[q * Lpad + t].x;
+              si += red[q * Lpad + t].y;
+            }
+            const bool act = ((bmask >> b) & 1u) && t < L;
+            if (t < (int)Lmax) brow[(size_t)b * Lmax + t] = act ? make_float2(sr, si) : make_float2(0.f, 0.f);
+          }
+        }
+        for (uint32_t k = t; k < d.Kmax * Lmax; k += kBWG) {
+          const uint32_t b = k / Lmax, l2 = k - b * Lmax;
+          if ((int)b >= KH || (int)l2 >= Lpad) brow[k] = make_float2(0.f, 0.f);
+        }
+      }
+    }
+    // ---- grad_x = S1 + (x^2/r^2) S2 for the inputs of this tile
+#pragma unroll
+    for (int j = 0; j < kBJ; ++j) {
+      const int m = n0 + t * kBJ + j;
+      if (m < n) {
+        float gr = s1r[j], gi = s1i[j];
+        const float r2 = xr[j] * xr[j] + xi[j] * xi[j];
+        if (r2 > 0.f) {
+          const float er = (xr[j] * xr[j] - xi[j] * xi[j]) / r2, ei = 2.f * xr[j] * xi[j] / r2;
+          gr += er * s2r[j] - ei * s2i[j];
+          gi += er * s2i[j] + ei * s2r[j];
+        }
+        F.gx[m] = make_float2(gr, gi);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Gradient of the Lmax-1 stream samples before each filter-bank frame (its
+// window's halo) from that frame's outputs: one workgroup per frame.
+__global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame *__restrict__ bf,
+                                                 float2 *__restrict__ hg) {
+  const uint32_t f = blockIdx.x;
+  if (f >= d.n_frames) return;
+  const BwdFrame F = bf[f];
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const int H = (int)Lmax - 1;
+  const int k = threadIdx.x;
+  if (k >= H) return;
+  const int m = k - H;                     // position relative to the frame start
+  float2 out = make_float2(0.f, 0.f);
+  if (!F.route && F.n && (int)F.t0 + m >= 0) {
+    const float2 xv = F.x[m];
+    const float r = sqrtf(xv.x * xv.x + xv.y * xv.y);
+    float s1r = 0.f, s1i = 0.f, s2r = 0.f, s2i = 0.f;
+    const uint32_t kfull = (1u << d.Kmax) - 1u;
+    for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+      const uint32_t bmask = (F.mask >> (bank * d.Kmax)) & kfull;
+      if (!bmask) continue;
+      const int KH = 32 - __clz(bmask);
+      const int L = (int)d.L[bank];
+      const float2 *tb = F.taps + (size_t)bank * d.Kmax * Lmax;
+      for (int l = -m; l < L && m + l < (int)F.n; ++l) {
+        float qr = 0.f, qi = 0.f, tr = 0.f, ti = 0.f;
+        for (int b = KH - 1; b >= 0; --b) {
+          float2 h = make_float2(0.f, 0.f);
+          if ((bmask >> b) & 1u) h = tb[(size_t)b * Lmax + l];
+          const float al = 0.5f * (float)b + 1.f, be = 0.5f * (float)b;
+          qr = fmaf(qr, r, al * h.x);
+          qi = fmaf(qi, r, -al * h.y);
+          tr = fmaf(tr, r, be * h.x);
+          ti = fmaf(ti, r, be * h.y);
+        }
+        const float2 gv = F.g[m + l];
+        s1r += gv.x * qr - gv.y * qi;
+        s1i += gv.x * qi + gv.y * qr;
+        s2r += gv.x * tr + gv.y * ti;
+        s2i += gv.x * ti - gv.y * tr;
+      }
+    }
+    const float r2 = xv.x * xv.x + xv.y * xv.y;
+    out = make_float2(s1r, s1i);
+    if (r2 > 0.f) {
+      const float er = (xv.x * xv.x - xv.y * xv.y) / r2, ei = 2.f * xv.x * xv.y / r2;
+      out.x += er * s2r - ei * s2i;
+      out.y += er * s2i + ei * s2r;
+    }
+  }
+  hg[(size_t)f * H + k] = out;
+}
+
+// Add later frames' halo gradients into grad_x (frames of a stream are
+// consecutive and in order).  Thread per (frame, one of its last H samples).
+__global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_frame *__restrict__ fr,
+                                                const BwdFrame *__restrict__ bf,
+                                                const float2 *__restrict__ hg) {
+  const uint32_t f = blockIdx.x;
+  if (f >= d.n_frames) return;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const int H = (int)Lmax - 1;
+  const BwdFrame F = bf[f];
+  const int k = threadIdx.x;
+  if (k >= H || !F.n) return;
+  const int local = (int)F.n - H + k;      // sample of this frame
+  if (local < 0) return;
+  const uint64_t q = (uint64_t)F.t0 + local;
+  float2 acc = F.gx[local];
+  for (uint32_t f2 = f + 1; f2 < d.n_frames; ++f2) {
+    const prune_fb_frame G = fr[f2];
+    if (G.stream != F.stream || (uint64_t)G.t0 > q + H) break;
+    if (G.route || !bf[f2].n) continue;
+    const int64_t pos = (int64_t)q - ((int64_t)G.t0 - H);   // index in G's halo
+    if (pos >= 0 && pos < H) {
+      const float2 v = hg[(size_t)f2 * H + pos];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+  }
+  F.gx[local] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_bwd_reduce1(prune_fb_desc d, const float2 *__restrict__ partial,
+                                                     const uint32_t *__restrict__ s_begin,
+                                                     const uint32_t *__restrict__ s_end,
+                                                     double2 *__restrict__ part2) {
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const uint32_t E = d.n_banks * d.Kmax * Lmax;
+  const uint32_t s = blockIdx.x, grp = blockIdx.y;
+  const uint32_t b0 = s_begin[s], b1 = s_end[s];
+  const uint32_t nch = (b1 - b0 + kRedChunk - 1) / kRedChunk;
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (uint32_t c = grp; c < nch; c += gridDim.y) {
+      const uint32_t lo = b0 + c * kRedChunk, hi = min(b1, lo + kRedChunk);
+      for (uint32_t t = lo; t < hi; ++t) {
+        const float2 v = partial[(size_t)t * E + e];
+        sr += v.x;
+        si += v.y;
+      }
+    }
+    part2[((size_t)s * gridDim.y + grp) * E + e] = make_double2(sr, si);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const double2 *__restrict__ part2,
+                                                     uint32_t groups, float2 *__restrict__ gtaps) {
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const uint32_t E = d.n_banks * d.Kmax * Lmax;
+  const uint32_t s = blockIdx.x;
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (uint32_t g = 0; g < groups; ++g) {
+      const double2 v = part2[((size_t)s * groups + g) * E + e];
+      sr += v.x;
+      si += v.y;
+    }
+    gtaps[(size_t)s * E + e] = make_float2((float)sr, (float)si);
+  }
+}
+
+struct BwdLayout {
+  size_t frames, items, partial, part2, hg, sbeg, send, cnt, total;
+  uint32_t max_items, E, H;
+};
+
+static BwdLayout bwd_layout(const prune_fb_desc &d) {
+  BwdLayout L{};
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = std::max(Lmax, d.L[b]);
+  L.E = d.n_banks * d.Kmax * Lmax;
+  L.H = Lmax - 1;
+  const size_t per = ((size_t)d.max_frame_len + kBT - 1) / kBT;
+  L.max_items = (uint32_t)std::max<size_t>(1, (size_t)d.n_frames * std::max<size_t>(per, 1));
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  size_t o = 0;
+  L.frames = o; o = al(o + (size_t)d.n_frames * sizeof(BwdFrame));
+  L.items = o; o = al(o + (size_t)L.max_items * sizeof(WorkItem));
+  L.partial = o; o = al(o + (size_t)L.max_items * L.E * sizeof(float2));
+  L.part2 = o; o = al(o + (size_t)d.n_streams * kRedG * L.E * sizeof(double2));
+  L.hg = o; o = al(o + (size_t)d.n_frames * std::max<uint32_t>(L.H, 1) * sizeof(float2));
+  L.sbeg = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
+  L.send = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
+  L.cnt = o; o = al(o + 16);
+  L.total = o;
+  return L;
+}
+
+static prune_status check_bwd_desc(const prune_fb_desc *d) {
+  if (!d || d->n_streams == 0 || d->n_banks < 1 || d->n_banks > PRUNE_MAX_BANKS || d->Kmax < 1 ||
+      d->Kmax > 10 || d->n_banks * d->Kmax > PRUNE_MAX_BRANCHES)
+    return PRUNE_E_UNSUPPORTED;
+  for (uint32_t b = 0; b < d->n_banks; ++b)
+    if (d->L[b] < 1 || d->L[b] > PRUNE_MAX_L) return PRUNE_E_UNSUPPORTED;
+  return PRUNE_OK;
+}
+
+}  // namespace prune
+
+using namespace prune;
+
+extern "C" {
+
+prune_status prune_fb_workspace_bytes(const prune_fb_desc *desc, size_t *bytes) {
+  prune_status st = check_bwd_desc(desc);
+  if (st != PRUNE_OK) return st;
+  if (!bytes) return PRUNE_E_ARG;
+  *bytes = bwd_layout(*desc).total;
+  return PRUNE_OK;
+}
+
 prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const void *taps,
                                const void *frames, const void *gy, void *gx, void *gtaps,
                                void *workspace, size_t workspace_bytes, prune_stream_t stream) {
-  (void)desc; (void)x; (void)taps; (void)frames; (void)gy; (void)gx; (void)gtaps;
-  (void)workspace; (void)workspace_bytes; (void)stream;
-  return PRUNE_E_UNSUPPORTED;
+  prune_status st = check_bwd_desc(desc);
+  if (st != PRUNE_OK) return st;
+  if (!x || !taps || !frames || !gy || !gx || !gtaps || !workspace) return PRUNE_E_ARG;
+  const BwdLayout L = bwd_layout(*desc);
+  if (workspace_bytes < L.total) return PRUNE_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  char *w = (char *)workspace;
+  BwdFrame *bf = (BwdFrame *)(w + L.frames);
+  WorkItem *items = (WorkItem *)(w + L.items);
+  float2 *partial = (float2 *)(w + L.partial);
+  double2 *part2 = (double2 *)(w + L.part2);
+  float2 *hg = (float2 *)(w + L.hg);
+  uint32_t *sb = (uint32_t *)(w + L.sbeg), *se = (uint32_t *)(w + L.send);
+  uint32_t *cnt = (uint32_t *)(w + L.cnt);
+  const prune_fb_desc d = *desc;
+  // grad_x starts as zero outside the frames' coverage
+  if (hipMemsetAsync(gx, 0, (size_t)d.n_streams * d.stream_len * sizeof(float2), s) != hipSuccess)
+    return PRUNE_E_HIP;
+  if (d.n_frames == 0) {
+    if (hipMemsetAsync(gtaps, 0, (size_t)d.n_streams * L.E * sizeof(float2), s) != hipSuccess)
+      return PRUNE_E_HIP;
+    return PRUNE_OK;
+  }
+  hipLaunchKernelGGL(k_bwd_prep, dim3(1), dim3(1024), 0, s, d, (const float2 *)x, (const float2 *)taps,
+                     (const prune_fb_frame *)frames, (const float2 *)gy, (float2 *)gx, bf, items, cnt,
+                     sb, se);
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
+  hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
+  if (L.H) {
+    hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
+    hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
+                       bf, hg);
+  }
+  hipLaunchKernelGGL(k_bwd_reduce1, dim3(d.n_streams, kRedG), dim3(256), 0, s, d, partial, sb, se, part2);
+  hipLaunchKernelGGL(k_bwd_reduce2, dim3(d.n_streams), dim3(256), 0, s, d, part2, (uint32_t)kRedG,
+                     (float2 *)gtaps);
+  return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }
-}
+
+}  // extern "C"

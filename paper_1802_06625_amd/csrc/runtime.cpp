@@ -144,14 +144,17 @@ struct prune_graph {
   uint32_t *d_halo_off = nullptr;
   uint32_t *d_ctr = nullptr;   // fb_count[nl], copy_count[nl], ticket[nl], gather_count[nl]
   GatherReq *d_gather = nullptr;
+  bool fast_batch = true;
+  BatchArgs bargs{};
+  std::vector<uint32_t> fifo_local;
   uint32_t *d_gather_off = nullptr;
   std::vector<uint32_t> gather_off, gather_cap;
   uint32_t *d_err = nullptr;
   prune_trace_record *d_trace = nullptr;
   uint64_t trace_cap = 0;
   unsigned long long *d_trace_count = nullptr;
-  std::map<uint32_t, hipGraphExec_t> graphs;
-  std::map<uint32_t, hipGraph_t> graph_defs;
+  std::map<uint64_t, hipGraphExec_t> graphs;
+  std::map<uint64_t, hipGraph_t> graph_defs;
   hipStream_t capture_stream = nullptr;
   int variant = 1;
   uint32_t tile = 2048;
@@ -366,6 +369,16 @@ prune_status build_device(prune_graph *g) {
     g->h_ports.push_back(d);
   }
   TRY(upload(g, &g->d_ports, g->h_ports));
+  // FIFO slots within their component (for the parallel batch decode)
+  g->fifo_local.assign(g->fifos.size(), 0);
+  {
+    std::vector<uint32_t> per_comp(g->n_comp, 0);
+    for (uint32_t f = 0; f < g->fifos.size(); ++f) {
+      const uint32_t cmp = g->actors[g->ports[g->fifos[f].src].actor].comp;
+      g->fifo_local[f] = per_comp[cmp]++;
+      if (g->fifo_local[f] >= (uint32_t)kMaxCompFifos) g->fast_batch = false;
+    }
+  }
   // fifos
   std::vector<FifoDev> hf(g->fifos.size());
   for (uint32_t f = 0; f < g->fifos.size(); ++f) {
@@ -385,6 +398,7 @@ prune_status build_device(prune_graph *g) {
     if (F.param) TRY(dalloc(g, &F.counts, d.blocks));
     d.base = (char *)F.storage;
     d.counts = F.counts;
+    d.pad = g->fifo_local[f];
   }
   TRY(upload(g, &g->d_fifos, hf));
   // filter banks
@@ -618,6 +632,46 @@ prune_status alloc_scratch(prune_graph *g) {
   TRY(upload(g, &g->d_iota, iota));
   std::vector<uint32_t> so = {0, 1};
   TRY(upload(g, &g->d_single_off, so));
+  // access table and per-iteration arrays of the parallel batch bookkeeping
+  std::vector<uint32_t> acc_off(na + 1, 0);
+  std::vector<AccDev> acc;
+  for (uint32_t a = 0; a < na; ++a) {
+    acc_off[a] = (uint32_t)acc.size();
+    uint32_t in_slot = 0, out_slot = 0, drp = 0;
+    for (uint32_t p : g->actors[a].ports) {
+      const HPort &P = g->ports[p];
+      if (P.kind == PRUNE_CPORT) continue;
+      const uint32_t my_drp = P.kind == PRUNE_DRP ? drp++ : kNone;
+      if (P.dir == PRUNE_IN) {
+        AccDev d{P.dev, P.fifos[0], PRUNE_IN, in_slot++, 1u, my_drp, g->fifo_local[P.fifos[0]], 0u};
+        acc.push_back(d);
+      } else {
+        for (size_t k = 0; k < P.fifos.size(); ++k) {
+          AccDev d{P.dev, P.fifos[k], PRUNE_OUT, out_slot++, k == 0 ? 1u : 0u, my_drp,
+                   g->fifo_local[P.fifos[k]], 0u};
+          acc.push_back(d);
+        }
+      }
+    }
+  }
+  acc_off[na] = (uint32_t)acc.size();
+  std::vector<uint32_t> fifo_wacc(g->fifos.size(), 0);
+  for (uint32_t k = 0; k < acc.size(); ++k)
+    if (acc[k].dir == PRUNE_OUT) fifo_wacc[acc[k].fifo] = k;
+  const size_t nacc = acc.size();
+  BatchArgs &b = g->bargs;
+  TRY(upload(g, (uint32_t **)&b.acc_off, acc_off));
+  TRY(upload(g, (AccDev **)&b.acc, acc));
+  uint32_t **soa[] = {&b.s_fired, &b.s_mask, &b.s_rate, &b.s_bitmap, &b.s_firing, &b.s_aux,
+                      &b.s_auxoff, &b.s_aux2};
+  for (uint32_t **q : soa) TRY(dalloc(g, q, (size_t)na * Bc));
+  TRY(dalloc(g, &b.s_cnt, nacc * Bc));
+  TRY(dalloc(g, &b.s_pre, nacc * Bc));
+  TRY(dalloc(g, &b.s_base, nacc));
+  TRY(dalloc(g, &b.s_qbase, na));
+  TRY(dalloc(g, &b.s_sink, na));
+  TRY(dalloc(g, &b.s_rsnap, g->fifos.size()));
+  TRY(upload(g, (uint32_t **)&b.fifo_wacc, fifo_wacc));
   return PRUNE_OK;
 }
 
@@ -627,6 +681,7 @@ CtrlArgs make_args(prune_graph *g, uint32_t B) {
   c.fifos = g->d_fifos; c.ports = g->d_ports; c.actors = g->d_actors; c.fbs = g->d_fbs;
   c.comp_off = g->d_comp_off; c.comp_actors = g->d_comp_actors;
   c.B = B; c.Bcap = g->Bcap; c.tile = g->tile; c.clear_n = 0;
+  c.n_fifos = (uint32_t)g->fifos.size();
   c.recs = g->d_recs; c.wrote = g->d_wrote;
   c.fb_desc = g->d_desc; c.desc_off = g->d_desc_off;
   c.fb_items = g->d_items; c.fb_item_off = g->d_item_off; c.fb_count = g->d_ctr;
@@ -789,21 +844,28 @@ prune_status check_graph(prune_graph *g, bool need_final, bool need_device = tru
 }
 
 prune_status ensure_ring(prune_graph *g, HActor &A, size_t entry, uint64_t need) {
+  (void)g;
   const uint64_t live = A.q_tail - A.q_head;
   if (A.q_dev && live + need <= A.q_cap) return PRUNE_OK;
   uint64_t cap = std::max<uint64_t>(1024, A.q_cap);
   while (cap < live + need) cap *= 2;
-  void *nq = nullptr;
+  char *nq = nullptr, *lin = nullptr;
   HIPCHECK(hipDeviceSynchronize());
-  HIPCHECK(hipMalloc(&nq, cap * entry));
+  HIPCHECK(hipMalloc((void **)&nq, cap * entry));
   if (A.q_dev && live) {
-    std::vector<char> tmp(live * entry);
-    for (uint64_t k = 0; k < live; ++k)
-      HIPCHECK(hipMemcpy(tmp.data() + k * entry, (char *)A.q_dev + ((A.q_head + k) % A.q_cap) * entry,
-                         entry, hipMemcpyDeviceToHost));
-    for (uint64_t k = 0; k < live; ++k)
-      HIPCHECK(hipMemcpy((char *)nq + ((A.q_head + k) % cap) * entry, tmp.data() + k * entry, entry,
-                         hipMemcpyHostToDevice));
+    // linearise the live entries, then place them at their positions mod cap
+    HIPCHECK(hipMalloc((void **)&lin, live * entry));
+    const uint64_t h = A.q_head % A.q_cap;
+    const uint64_t run1 = std::min<uint64_t>(live, A.q_cap - h);
+    HIPCHECK(hipMemcpy(lin, (char *)A.q_dev + h * entry, run1 * entry, hipMemcpyDeviceToDevice));
+    if (live > run1)
+      HIPCHECK(hipMemcpy(lin + run1 * entry, A.q_dev, (live - run1) * entry, hipMemcpyDeviceToDevice));
+    const uint64_t h2 = A.q_head % cap;
+    const uint64_t run2 = std::min<uint64_t>(live, cap - h2);
+    HIPCHECK(hipMemcpy(nq + h2 * entry, lin, run2 * entry, hipMemcpyDeviceToDevice));
+    if (live > run2)
+      HIPCHECK(hipMemcpy(nq, lin + run2 * entry, (live - run2) * entry, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipFree(lin));
   }
   if (A.q_dev) HIPCHECK(hipFree(A.q_dev));
   A.q_dev = nq;
@@ -825,12 +887,51 @@ prune_status ring_write(HActor &A, size_t entry, const void *host, uint64_t n) {
   return PRUNE_OK;
 }
 
+// Levels whose copy kernel can have work in this batch, and levels whose
+// stateful actors can see a previous frame shorter than their history.
+void launch_masks(prune_graph *g, uint32_t B, uint64_t *copy_mask, uint64_t *gather_mask) {
+  *copy_mask = 0;
+  *gather_mask = 0;
+  for (auto &A : g->actors) {
+    const uint64_t bit = 1ull << std::min<uint32_t>(A.level, 63);
+    if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_SELECT || A.kind == PRUNE_PASSTHROUGH) *copy_mask |= bit;
+    if (A.kind == PRUNE_SINK && A.sink_out) *copy_mask |= bit;
+    if (A.kind == PRUNE_SOURCE) {
+      for (uint32_t k = 0; k < B && k < A.src_q.size(); ++k)
+        if (A.src_q[k].ptr) { *copy_mask |= bit; break; }
+    }
+    if (A.hist_len && B > 1) {
+      for (uint32_t p : A.ports) {
+        const HPort &P = g->ports[p];
+        if (P.dir == PRUNE_IN && P.kind == PRUNE_SRP &&
+            ((P.flags & PRUNE_PORT_PARAM) || P.atr < A.hist_len))
+          *gather_mask |= bit;
+      }
+    }
+  }
+}
+
 prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph) {
+  uint64_t cmask, gmask;
+  launch_masks(g, B, &cmask, &gmask);
   auto enqueue = [&](hipStream_t st) {
-    launch_clear(g->d_ctr, 4 * g->n_levels, st);
     CtrlArgs c = make_args(g, B);
-    launch_control(c, g->n_comp, st);
-    for (uint32_t l = 0; l < g->n_levels; ++l) launch_level(g, l, st, g->fb_grid, 0xffffffffu, B);
+    if (g->fast_batch) {
+      c.clear_n = 4 * g->n_levels;
+      launch_batch(c, g->bargs, g->n_comp, (uint32_t)g->actors.size(), st);
+    } else {
+      launch_clear(g->d_ctr, 4 * g->n_levels, st);
+      launch_control(c, g->n_comp, st);
+    }
+    for (uint32_t l = 0; l < g->n_levels; ++l) {
+      const uint64_t bit = 1ull << std::min<uint32_t>(l, 63);
+      if ((gmask & bit) && g->gather_cap[l])
+        launch_gather(make_args(g, B), l, std::min<uint32_t>(g->gather_cap[l], 256), st);
+      if ((cmask & bit) && g->level_copy[l])
+        launch_copy(g->d_copy + g->copy_item_off[l], g->d_ctr + g->n_levels + l,
+                    g->copy_item_cap[l], g->copy_max_total[l], st);
+      if (g->level_fb[l]) fb_launch_timed(g, l, g->fb_grid, st);
+    }
     launch_post(c, g->d_post_actors, (uint32_t)g->post_actors.size(), st);
   };
   if (!use_graph) {
@@ -838,7 +939,8 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
     HIPCHECK(hipGetLastError());
     return PRUNE_OK;
   }
-  auto it = g->graphs.find(B);
+  const uint64_t key = (uint64_t)B | (cmask << 20) | (gmask << 42);
+  auto it = g->graphs.find(key);
   if (it == g->graphs.end()) {
     if (!g->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
     HIPCHECK(hipStreamSynchronize(s));
@@ -851,8 +953,8 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
     g_timing = was;
     hipGraphExec_t exec = nullptr;
     HIPCHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    g->graph_defs[B] = graph;
-    it = g->graphs.emplace(B, exec).first;
+    g->graph_defs[key] = graph;
+    it = g->graphs.emplace(key, exec).first;
   }
   HIPCHECK(hipGraphLaunch(it->second, s));
   return PRUNE_OK;

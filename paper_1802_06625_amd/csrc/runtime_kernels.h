@@ -31,7 +31,7 @@ struct CtrlArgs {
   const uint32_t *comp_off;      // [n_comp + 1]
   const uint32_t *comp_actors;   // actors of each component in topological order
   uint32_t B, Bcap, tile, clear_n;
-  uint32_t per_firing, pad_;
+  uint32_t per_firing, n_fifos;
   FiringRec *recs;               // [n_actors][Bcap]
   uint32_t *wrote;               // [n_fifos][Bcap] tokens written per iteration
   FbFrameDesc *fb_desc;
@@ -53,6 +53,32 @@ struct CtrlArgs {
   TraceBuf trace;
 };
 
+// Parallel bookkeeping of a batch (three phases): decode per (component,
+// iteration), scans per component, emission per (component, iteration).
+constexpr int kMaxCompFifos = 24;
+
+struct AccDev {            // one (port, fifo) data access of an actor, in port order
+  uint32_t port, fifo, dir, slot;   // slot: ordinal among the actor's inputs or outputs
+  uint32_t first;                   // first FIFO of its port
+  uint32_t drp;                     // DRP ordinal of its port, kNone otherwise
+  uint32_t local;                   // FIFO slot within the component (< kMaxCompFifos)
+  uint32_t pad;
+};
+
+struct BatchArgs {
+  const uint32_t *acc_off;     // [n_actors + 1]
+  const AccDev *acc;
+  uint32_t *s_fired, *s_mask, *s_rate, *s_bitmap, *s_firing, *s_aux, *s_auxoff, *s_aux2;
+  uint32_t *s_cnt, *s_pre;     // [n_acc][Bcap]
+  uint64_t *s_base;            // [n_acc] FIFO index at batch start
+  uint64_t *s_qbase;           // [n_actors] queue head / control-FIFO read index at batch start
+  uint64_t *s_sink;            // [n_actors] sink output offset at batch start
+  uint64_t *s_rsnap;           // [n_fifos] tokens read before the batch
+  const uint32_t *fifo_wacc;   // [n_fifos] index of the FIFO's writer access
+};
+
+void launch_batch(const CtrlArgs &c, const BatchArgs &b, uint32_t n_comp, uint32_t n_actors,
+                  hipStream_t s);
 void launch_control(const CtrlArgs &c, uint32_t n_comp, hipStream_t s);
 void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x,
                  uint32_t max_total, hipStream_t s);
