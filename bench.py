@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-per-frame", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--only-c2", action="store_true", help="skip the other workloads")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="only copy a 1 GiB buffer twice (HBM counter calibration)")
     p.add_argument("--profile-only", action="store_true",
                    help="only the timed batched steps (for profiler runs)")
     return p.parse_args()
@@ -91,6 +94,15 @@ def main():
     from paper_1802_06625_amd.graph import PlainGraph
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b_ = torch.empty_like(a)
+        for _ in range(2):
+            b_.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read_per_dispatch": 1 << 30,
+                          "copy_calib_bytes_written_per_dispatch": 1 << 30}))
+        return
     print("bench: drawing C2 workload", file=sys.stderr, flush=True)
     wl = synth.make("C2", n_frames=args.frames or None)
     side = wl.side[0]
@@ -185,11 +197,156 @@ def main():
         out["per_frame_msamples"] = round(samples / el / 1e6, 1)
         out["batched_vs_per_frame"] = round(value / out["per_frame_msamples"], 1)
 
+    del g, pg
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.only_c2:
+        print("bench: fwd+bwd (differentiation workload)", file=sys.stderr, flush=True)
+        out["c4_fwd_bwd"] = bench_direct("C4", args.steps, args.warmup)
+        print("bench: batched uneven frames", file=sys.stderr, flush=True)
+        out["c3_batched"] = bench_c3(args.steps, args.warmup)
+        print("bench: routed multi-stream graph", file=sys.stderr, flush=True)
+        out["c5_routed"] = bench_c5(args.steps, args.warmup)
+        out["c5_fwd_bwd"] = bench_direct("C5", args.steps, args.warmup)
+
     if not args.no_cpu_baseline:
         print("bench: oracle baseline", file=sys.stderr, flush=True)
         wl2 = synth.make("C2", n_frames=args.frames or None)
         out["cpu_baseline"] = cpu_baseline(wl2, args.cpu_seconds, first)
     print(json.dumps(out))
+
+
+def _time_events(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_direct(name, steps, warmup):
+    """Forward and forward+adjoint of the filter bank over whole streams
+    (prune_fb_forward / prune_fb_backward) on a workload; the cotangent is the
+    workload's seeded one."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import ops
+    wl = synth.make(name, cotangent=True)
+    S, N = wl.x.shape
+    routed = wl.spec.pass_prob > 0
+    rows = ops.frames_from_side(wl.side, wl.Kmax, routed)
+    fr = ops.frame_table(rows)
+    mfl = int(wl.side[:, :, 1].max())
+    x = torch.from_numpy(wl.x).cuda()
+    taps = torch.from_numpy(wl.taps).cuda()
+    gy = torch.from_numpy(wl.gy).cuda()
+    y, gx, gt = torch.empty_like(x), torch.empty_like(x), torch.empty_like(taps)
+    work = torch.empty(ops.workspace_bytes(S, N, wl.Kmax, wl.bank_L, len(rows), mfl), dtype=torch.uint8,
+                       device="cuda")
+    fwd = lambda: ops.fb_forward(x, taps, fr, wl.Kmax, wl.bank_L, mfl, y=y)
+    bwd = lambda: ops.fb_backward(x, taps, fr, gy, wl.Kmax, wl.bank_L, mfl, gx=gx, gt=gt, work=work)
+    t_f = _time_events(fwd, steps, warmup)
+    t_b = _time_events(bwd, steps, warmup)
+    L = wl.bank_L[0]
+    side = wl.side.reshape(-1, 4)
+    fb_n = np.array([n for (_, _, n, _, r) in rows if not r], dtype=np.float64)
+    fb_k = np.array([wl.Kmax if routed else int(side[k, 0]) for k, (_, _, n, _, r) in enumerate(rows) if not r],
+                    dtype=np.float64)
+    f_fwd = float(np.sum(fb_n * (4.0 + fb_k * (8.0 * L + 3.0))))
+    f_bwd = float(np.sum(fb_n * (10.0 + fb_k * (16.0 * L + 17.0))))
+    samples = S * N
+    res = {"workload": wl.spec.description, "samples": samples,
+           "fwd_msamples": round(samples / (t_f * 1e-3) / 1e6, 1),
+           "fwd_bwd_msamples": round(samples / ((t_f + t_b) * 1e-3) / 1e6, 1),
+           "fwd_ms": round(t_f, 4), "bwd_ms": round(t_b, 4),
+           "fwd_tflops_alg": round(f_fwd / (t_f * 1e-3) / 1e12, 2),
+           "bwd_tflops_alg": round(f_bwd / (t_b * 1e-3) / 1e12, 2),
+           "fwd_bwd_frac_of_fp32_vector_peak": round((f_fwd + f_bwd) / ((t_f + t_b) * 1e-3) / 1e12
+                                                      / PEAK_FP32_VECTOR_TFLOPS, 4)}
+    del x, taps, gy, y, gx, gt, work
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_c3(steps, warmup):
+    """Batched uneven frames: 2048 frames with log-uniform rates in
+    [256, 65536], three tap banks, one hipGraph replay per batch."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import PlainGraph
+    wl = synth.make("C3")
+    side = wl.side[0]
+    F, atr = side.shape[0], int(wl.spec.n_max)
+    n = side[:, 1].astype(np.int64)
+    pg = PlainGraph(wl.Kmax, wl.bank_L, atr, F, param=True)
+    g = pg.g
+    g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    off = np.concatenate([[0], np.cumsum(n)])
+    x = torch.from_numpy(wl.x[0]).cuda()
+    blocks = pg.fifo_in.view(F, atr)
+    for f in range(F):
+        blocks[f, :n[f]] = x[off[f]:off[f + 1]]
+    del x
+    for _ in range(steps + warmup + 1):
+        g.source_push(pg.src, None, n)
+        g.config_push(pg.cfg, side)
+    torch.cuda.synchronize()
+    g.fire(L.BATCHED_GRAPH, F)
+    ms = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
+    g.sync()
+    samples = int(n.sum())
+    Lb = np.array(wl.bank_L, dtype=np.float64)[side[:, 2]]
+    flops = float(np.sum(n * (4.0 + side[:, 0] * (8.0 * Lb + 3.0))))
+    res = {"workload": wl.spec.description, "samples": samples, "frames": F,
+           "msamples": round(samples / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
+           "tflops_alg": round(flops / (ms * 1e-3) / 1e12, 2),
+           "frac_of_fp32_vector_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)}
+    del g, pg
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_c5(steps, warmup):
+    """Routed multi-stream graph: 64 independent switch/filter-bank/
+    passthrough/select streams of 16 frames x 32768, one hipGraph replay for
+    all streams."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import RoutedGraph
+    wl = synth.make("C5")
+    S, F, n = wl.n_streams, wl.n_frames, int(wl.side[0, 0, 1])
+    rg = RoutedGraph(S, wl.Kmax, wl.bank_L, n, F)
+    g = rg.g
+    for s, ids in enumerate(rg.streams):
+        g.set_taps(ids["fb"], torch.from_numpy(wl.taps[s]).cuda())
+        rg.storage[s]["in"].view(F, n).copy_(torch.from_numpy(wl.x[s]).view(F, n))
+        for _ in range(steps + warmup + 1):
+            g.source_push(ids["src"], None, wl.side[s, :, 1])
+            g.config_push(ids["cfg"], wl.side[s])
+    torch.cuda.synchronize()
+    g.fire(L.BATCHED_GRAPH, F)
+    ms = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
+    g.sync()
+    samples = S * F * n
+    n_fb = int((wl.side[:, :, 3] == 0).sum())
+    Lt = wl.bank_L[0]
+    flops = float(n_fb * n * (4.0 + wl.Kmax * (8.0 * Lt + 3.0)))
+    res = {"workload": wl.spec.description, "samples": samples,
+           "passthrough_frames": int(S * F - n_fb),
+           "msamples": round(samples / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
+           "tflops_alg": round(flops / (ms * 1e-3) / 1e12, 2)}
+    del g, rg
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -21,8 +21,8 @@ design notes):
   most once per sweep; a dynamic actor peeks its control token, decodes it,
   checks availability of the decoded rates, and only then consumes it.
 * Termination: the run ends when no actor can fire; it is a deadlock unless
-  every source and configuration actor has emitted all pushed input and every
-  FIFO holds exactly its delay tokens.
+  every source and configuration actor has emitted all pushed input and no
+  FIFO still holds a block its reader could take.
 
 Parity: pinned by tests/test_oracle_moc.py (the Fig. 6 worked example, Eq. 2
 in both cases, Eq. 1 and the control-table example, the Fig. 1 rates, token
@@ -670,8 +670,13 @@ class Graph:
         return total
 
     def _check_termination(self):
+        # Blocking reads (Sec. III-A): a consumer stalls while its FIFO holds
+        # fewer tokens than its rate.  A run that stops with external input
+        # pending, or with a FIFO still holding a readable block, has a stalled
+        # consumer; leftover tokens short of a block (delays that are not a
+        # multiple of the rate) are a normal end.
         pending = [a.id for a in self.actors if a.kind in (SOURCE, CONFIG) and a.state["queue"]]
-        stuck = [f.id for f in self.fstate if f.occupancy != f.Q]
+        stuck = [f.id for f in self.fstate if f.can_read()]
         if pending or stuck:
             raise PruneError(E_DEADLOCK, f"no actor can fire; pending inputs {pending}, "
                                          f"fifos holding tokens {stuck}")

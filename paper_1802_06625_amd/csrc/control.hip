@@ -501,6 +501,22 @@ __global__ __launch_bounds__(64) void k_gather(CtrlArgs c, uint32_t level) {
   }
 }
 
+// Copy-back of a FIFO with an unaligned delay (the access pattern of Fig. 6):
+// after a write whose slots run past rC-1, the tokens in the overflow area
+// [rC, end) are copied to [0, end-rC).  Per-firing launches only; `k` is the
+// write's index among the actor's output accesses.
+__global__ __launch_bounds__(256) void k_copyback(CtrlArgs c, uint32_t a, uint32_t fifo, uint32_t k) {
+  const FiringRec &r = c.recs[(size_t)a * c.Bcap];
+  if (!r.fired || k >= (uint32_t)kMaxIO || !r.out[k].ptr) return;
+  const FifoDev &f = c.fifos[fifo];
+  const uint64_t rc = (uint64_t)f.r * f.C;
+  const uint64_t slot = (uint64_t)(r.out[k].ptr - f.base) / f.token_bytes;
+  const uint64_t end = slot + f.r;
+  if (end <= rc) return;
+  const uint64_t nbytes = (end - rc) * f.token_bytes;
+  for (uint64_t q = threadIdx.x; q < nbytes; q += blockDim.x) f.base[q] = f.base[rc * f.token_bytes + q];
+}
+
 // Zero the per-level counters and work tickets (a fill kernel rather than a
 // memset so the sequence can be captured into a graph).
 __global__ void k_clear_u32(uint32_t *p, uint32_t n) {
@@ -529,6 +545,10 @@ void launch_post(const CtrlArgs &c, const uint32_t *actors, uint32_t n, hipStrea
 void launch_gather(const CtrlArgs &c, uint32_t level, uint32_t grid, hipStream_t s) {
   if (!grid) return;
   hipLaunchKernelGGL(k_gather, dim3(grid), dim3(64), 0, s, c, level);
+}
+
+void launch_copyback(const CtrlArgs &c, uint32_t a, uint32_t fifo, uint32_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_copyback, dim3(1), dim3(256), 0, s, c, a, fifo, k);
 }
 
 void launch_clear(uint32_t *p, uint32_t n, hipStream_t s) {

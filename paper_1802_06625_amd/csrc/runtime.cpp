@@ -825,6 +825,17 @@ prune_status fire_one(prune_graph *g, uint32_t aid, hipStream_t s) {
                   std::max<uint32_t>(1, out_accesses(g, A)), max_count, s);
   }
   if (A.hist_len) launch_post(c, g->d_iota + aid, 1, s);
+  // FIFOs with an unaligned delay: copy the overflow of this write back
+  uint32_t k = 0;
+  for (uint32_t p : A.ports) {
+    const HPort &P = g->ports[p];
+    if (P.kind == PRUNE_CPORT || P.dir != PRUNE_OUT) continue;
+    for (uint32_t f : P.fifos) {
+      const HFifo &F = g->fifos[f];
+      if (F.delay % F.rate) launch_copyback(c, aid, f, k, s);
+      ++k;
+    }
+  }
   return PRUNE_OK;
 }
 

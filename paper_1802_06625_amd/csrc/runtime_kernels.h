@@ -85,6 +85,7 @@ void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x
 void launch_post(const CtrlArgs &c, const uint32_t *actors, uint32_t n, hipStream_t s);
 void launch_gather(const CtrlArgs &c, uint32_t level, uint32_t grid, hipStream_t s);
 void launch_clear(uint32_t *p, uint32_t n, hipStream_t s);
+void launch_copyback(const CtrlArgs &c, uint32_t a, uint32_t fifo, uint32_t k, hipStream_t s);
 
 int fb_variant_count();
 const char *fb_variant_name(int v);

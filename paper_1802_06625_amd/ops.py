@@ -26,6 +26,30 @@ def make_desc(n_streams, stream_len, Kmax, bank_L, n_frames, max_frame_len):
     return d
 
 
+def frames_from_side(side, Kmax, routed):
+    """Frame rows (stream, t0, n, mask, route) of a batch of streams from the
+    configuration actor's side-information [S, F, 4] (K, n, bank, route),
+    using the library's own configuration mapping (prune_rule_config_token).
+    Routed streams run every branch on filter-bank frames."""
+    side = np.asarray(side, dtype=np.uint32)
+    S, F, _ = side.shape
+    rows = []
+    tok = L.CtrlToken()
+    for s_ in range(S):
+        t0 = 0
+        for f in range(F):
+            K, n, bank, route = (int(v) for v in side[s_, f])
+            if routed:
+                mask, r = 0xFFFFFFFF, route
+            else:
+                si = L.SideInfo(K, n, bank, route)
+                call("prune_rule_config_token", L.CONFIG_PREFIX, Kmax, C.byref(si), C.byref(tok))
+                mask, r = tok.mask, 0
+            rows.append((s_, t0, n, mask, r))
+            t0 += n
+    return rows
+
+
 def frame_table(frames, device="cuda"):
     """frames: array [F, 5] of (stream, t0, n, mask, route) -> device table of
     prune_fb_frame records (8 x uint32)."""
@@ -38,20 +62,28 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def fb_forward(x, taps, frames_dev, Kmax, bank_L, max_frame_len):
+def fb_forward(x, taps, frames_dev, Kmax, bank_L, max_frame_len, y=None):
     """x: complex64 [S, N] (cuda); taps: complex64 [S, n_banks, Kmax, Lmax];
     frames_dev: frame_table(...).  Returns y [S, N]."""
     S, N = x.shape
     x = x.contiguous()
     taps = taps.contiguous()
-    y = torch.empty_like(x)
+    if y is None:
+        y = torch.empty_like(x)
     d = make_desc(S, N, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
     call("prune_fb_forward", C.byref(d), C.c_void_p(x.data_ptr()), C.c_void_p(taps.data_ptr()),
          C.c_void_p(frames_dev.data_ptr()), C.c_void_p(y.data_ptr()), _stream())
     return y
 
 
-def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len):
+def workspace_bytes(S, N, Kmax, bank_L, n_frames, max_frame_len):
+    d = make_desc(S, N, Kmax, bank_L, n_frames, max_frame_len)
+    ws = C.c_size_t()
+    call("prune_fb_workspace_bytes", C.byref(d), C.byref(ws))
+    return ws.value
+
+
+def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len, gx=None, gt=None, work=None):
     S, N = x.shape
     x = x.contiguous()
     taps = taps.contiguous()
@@ -59,9 +91,12 @@ def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len):
     d = make_desc(S, N, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
     ws = C.c_size_t()
     call("prune_fb_workspace_bytes", C.byref(d), C.byref(ws))
-    work = torch.empty(max(1, ws.value), dtype=torch.uint8, device=x.device)
-    gx = torch.empty_like(x)
-    gt = torch.empty_like(taps)
+    if work is None or work.numel() < ws.value:
+        work = torch.empty(max(1, ws.value), dtype=torch.uint8, device=x.device)
+    if gx is None:
+        gx = torch.empty_like(x)
+    if gt is None:
+        gt = torch.empty_like(taps)
     call("prune_fb_backward", C.byref(d), C.c_void_p(x.data_ptr()), C.c_void_p(taps.data_ptr()),
          C.c_void_p(frames_dev.data_ptr()), C.c_void_p(gy.data_ptr()), C.c_void_p(gx.data_ptr()),
          C.c_void_p(gt.data_ptr()), C.c_void_p(work.data_ptr()), ws.value, _stream())

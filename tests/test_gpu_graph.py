@@ -124,3 +124,48 @@ def test_rate_beyond_atr_is_reported():
     with pytest.raises(L.PruneError) as e:
         g.sync()
     assert e.value.code == L.E_TOKEN
+
+
+@pytest.mark.parametrize("r,Q,C", [(4, 1, 3), (4, 5, 2), (4, 4, 3), (6, 3, 2)])
+def test_delay_fifo_per_firing(r, Q, C):
+    """A delayed channel (Fig. 6 access pattern, copy-back included) delivers Q
+    zero tokens then the stream; slots and counters match the oracle."""
+    announce(f"delay fifo r={r} Q={Q} C={C}")
+    from oracle.moc import Graph as OG, SOURCE as OS, PASSTHROUGH as OP, SINK as OK_, IN as OI, \
+        OUT as OO, SRP as OSRP
+    from paper_1802_06625_amd.graph import Graph
+    n_blocks = 9
+    data = (np.arange(r * n_blocks) + 1.0).astype(np.complex64) * (1 - 0.5j)
+    og = OG()
+    a, b, c_ = og.actor(OS), og.actor(OP), og.actor(OK_)
+    pa, pb = og.port(a, OO, OSRP, r), og.port(b, OI, OSRP, r)
+    pc, pd = og.port(b, OO, OSRP, r), og.port(c_, OI, OSRP, r)
+    og.connect(pa, pb, r, Q)
+    og.connect(pc, pd, r)
+    og.finalize(C)
+    og.push(a, [data[k * r:(k + 1) * r] for k in range(n_blocks)])
+    og.run()
+    ref = og.sink_output(c_)
+    logs = og.logs()
+    g = Graph(0)
+    ga, gb, gc = g.actor(L.SOURCE), g.actor(L.PASSTHROUGH), g.actor(L.SINK)
+    qa, qb = g.port(ga, L.OUT, L.SRP, r), g.port(gb, L.IN, L.SRP, r)
+    qc, qd = g.port(gb, L.OUT, L.SRP, r), g.port(gc, L.IN, L.SRP, r)
+    f0 = g.connect(qa, qb, r, Q)
+    f1 = g.connect(qc, qd, r)
+    g.finalize(C)
+    g.alloc_fifo(f0)
+    g.alloc_fifo(f1)
+    out = torch.zeros(len(ref) + r, dtype=torch.complex64, device="cuda")
+    g.sink_bind_output(gc, out)
+    g.trace_enable(4096)
+    g.source_push(ga, torch.from_numpy(data).cuda(), [r] * n_blocks)
+    g.fire(L.PER_FIRING)
+    g.sync()
+    y = out.cpu().numpy()[:len(ref)]
+    np.testing.assert_array_equal(y, ref.astype(np.complex64))
+    from paper_1802_06625_amd.graph import trace_logs
+    fifos, _ = trace_logs(g.trace_fetch())
+    for fid in (0, 1):
+        assert fifos[fid]["writes"] == [tuple(w) for w in logs["fifos"][fid]["writes"]]
+        assert fifos[fid]["reads"] == [tuple(w) for w in logs["fifos"][fid]["reads"]]
