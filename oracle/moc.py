@@ -20,9 +20,9 @@ design notes):
 * Scheduling: round-robin over actors in creation order, each actor fires at
   most once per sweep; a dynamic actor peeks its control token, decodes it,
   checks availability of the decoded rates, and only then consumes it.
-* Termination: the run ends when no actor can fire; it is a deadlock unless
-  every source and configuration actor has emitted all pushed input and no
-  FIFO still holds a block its reader could take.
+* Termination: the run ends when no actor can fire; it is a deadlock when
+  external input is still pending or a dynamic actor holds a control token
+  it cannot act on.
 
 Parity: pinned by tests/test_oracle_moc.py (the Fig. 6 worked example, Eq. 2
 in both cases, Eq. 1 and the control-table example, the Fig. 1 rates, token
@@ -670,16 +670,18 @@ class Graph:
         return total
 
     def _check_termination(self):
-        # Blocking reads (Sec. III-A): a consumer stalls while its FIFO holds
-        # fewer tokens than its rate.  A run that stops with external input
-        # pending, or with a FIFO still holding a readable block, has a stalled
-        # consumer; leftover tokens short of a block (delays that are not a
-        # multiple of the rate) are a normal end.
+        # With finite input a run always stops; it is stuck (rather than out of
+        # input) when external input is still pending, or when a dynamic actor
+        # holds a control token yet cannot fire: it waits on data that no
+        # firing will produce (the linked-DRP deadlock of Sec. V).  Tokens
+        # left behind by delays are a normal end.
         pending = [a.id for a in self.actors if a.kind in (SOURCE, CONFIG) and a.state["queue"]]
-        stuck = [f.id for f in self.fstate if f.can_read()]
-        if pending or stuck:
+        stalled = [a.id for a in self.actors if a.kind not in (SOURCE, CONFIG)
+                   and self.cport(a.id) is not None
+                   and self.fstate[self.cport(a.id).fifos[0]].can_read()]
+        if pending or stalled:
             raise PruneError(E_DEADLOCK, f"no actor can fire; pending inputs {pending}, "
-                                         f"fifos holding tokens {stuck}")
+                                         f"dynamic actors holding control tokens {stalled}")
 
     # ---- results -------------------------------------------------------------
     def sink_output(self, aid):
