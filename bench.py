@@ -46,6 +46,18 @@ def parse():
     return p.parse_args()
 
 
+def measured_traffic(kernel_src, record):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(record) if "=" in l)
+        h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+        return float(kv["traffic_bytes"]) if kv.get("source_sha256_16") == h else None
+    except OSError:
+        return None
+
+
 def algorithmic_flops(side, L):
     """Direct-form flops of the forward: per sample 4 (|x|) + K (8L + 3)."""
     n = side[:, 1].astype(np.float64)
@@ -114,6 +126,7 @@ def main():
 
     print("bench: building graph", file=sys.stderr, flush=True)
     pg = PlainGraph(wl.Kmax, wl.bank_L, n, F)
+    g_variant = ops.autotuned_variant(Lt, wl.Kmax, n)
     g = pg.g
     g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
     pg.fifo_in.view(F, n).copy_(torch.from_numpy(wl.x[0]).view(F, n))
@@ -156,7 +169,7 @@ def main():
                                   f"from control tokens, L={Lt} taps, batched hipGraph replay",
                       "frames": F, "frame_len": n, "taps": Lt, "Kmax": wl.Kmax,
                       "samples_per_step": samples, "mode": "batched_graph",
-                      "fb_variant": None},
+                      "fb_variant": ops.variant_names()[g_variant - 1] if g_variant else None},
            "event_ms_per_step": round(ev_ms_step, 4)}
     if args.profile_only:
         print(json.dumps(out))
@@ -174,9 +187,12 @@ def main():
     ops.timing_enable(False)
     k_ms = float(np.mean(kms))
     achieved = flops / (k_ms * 1e-3) / 1e12
+    traffic = measured_traffic(os.path.join(ROOT, "paper_1802_06625_amd", "csrc", "fb_forward.hip"),
+                               os.path.join(ROOT, "profiles", "fb_forward_c2_traffic.txt"))
     out["roofline"] = {"bound": "alu", "achieved": round(achieved, 2),
                        "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                       "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                       "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                       "traffic_algorithmic": 16.0 * samples,
                        "kernel": "k_fb_forward", "kernel_ms": round(k_ms, 4),
                        "algorithmic_flops_per_launch": flops,
                        "hbm_gbps_algorithmic": round(16.0 * samples / (k_ms * 1e-3) / 1e9, 1)}

@@ -136,6 +136,13 @@ def variant_names():
     return [L.lib().prune_fb_variant_name(v).decode() for v in range(1, n + 1)]
 
 
+def autotuned_variant(L, K, n):
+    """Forward variant the autotuner picks for this shape class (1-based)."""
+    v = C.c_int()
+    call("prune_autotune_fb", int(L), int(K), int(n), C.byref(v))
+    return v.value
+
+
 def timing_enable(on=True):
     call("prune_timing_enable", int(on))
 
