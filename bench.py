@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--no-per-frame", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--only-c2", action="store_true", help="skip the other workloads")
+    p.add_argument("--only", default="", help="run one secondary workload only: c3, c4, c5, c5bwd")
     p.add_argument("--copy-calib", action="store_true",
                    help="only copy a 1 GiB buffer twice (HBM counter calibration)")
     p.add_argument("--profile-only", action="store_true",
@@ -106,6 +107,13 @@ def main():
     from paper_1802_06625_amd.graph import PlainGraph
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.only:
+        fn = {"c3": lambda: bench_c3(args.steps, args.warmup),
+              "c4": lambda: bench_direct("C4", args.steps, args.warmup),
+              "c5": lambda: bench_c5(args.steps, args.warmup),
+              "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup)}[args.only]
+        print(json.dumps({args.only: fn()}))
+        return
     if args.copy_calib:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b_ = torch.empty_like(a)
@@ -270,6 +278,23 @@ def bench_direct(name, steps, warmup):
     bwd = lambda: ops.fb_backward(x, taps, fr, gy, wl.Kmax, wl.bank_L, mfl, gx=gx, gt=gt, work=work)
     t_f = _time_events(fwd, steps, warmup)
     t_b = _time_events(bwd, steps, warmup)
+    bwd_by_form = {}
+    for form in (1, 2):
+        ops.set_bwd_variant(form)
+        try:
+            bwd_by_form[ops.bwd_variant_name(form)] = round(_time_events(bwd, steps, warmup), 4)
+        finally:
+            ops.set_bwd_variant(0)
+    by_variant = {}
+    if name == "C5":
+        # every forward kernel forced in turn (vector Horner and matrix-core
+        # block-Toeplitz), same launch configuration as the autotuned call
+        for v, vname in enumerate(ops.variant_names(), start=1):
+            ops.set_variant(v)
+            try:
+                by_variant[vname] = round(_time_events(fwd, steps, warmup), 4)
+            finally:
+                ops.set_variant(0)
     L = wl.bank_L[0]
     side = wl.side.reshape(-1, 4)
     fb_n = np.array([n for (_, _, n, _, r) in rows if not r], dtype=np.float64)
@@ -285,7 +310,14 @@ def bench_direct(name, steps, warmup):
            "fwd_tflops_alg": round(f_fwd / (t_f * 1e-3) / 1e12, 2),
            "bwd_tflops_alg": round(f_bwd / (t_b * 1e-3) / 1e12, 2),
            "fwd_bwd_frac_of_fp32_vector_peak": round((f_fwd + f_bwd) / ((t_f + t_b) * 1e-3) / 1e12
-                                                      / PEAK_FP32_VECTOR_TFLOPS, 4)}
+                                                      / PEAK_FP32_VECTOR_TFLOPS, 4),
+           "fwd_variant": ops.variant_names()[ops.autotuned_variant(L, wl.Kmax, mfl) - 1],
+           "bwd_form": ops.bwd_variant_name(ops.autotuned_bwd_variant(L, wl.Kmax, mfl)),
+           "bwd_ms_by_form": bwd_by_form}
+    if by_variant:
+        res["fwd_ms_by_variant"] = by_variant
+        res["fwd_tflops_alg_by_variant"] = {k: round(f_fwd / (v * 1e-3) / 1e12, 2)
+                                            for k, v in by_variant.items()}
     del x, taps, gy, y, gx, gt, work
     torch.cuda.empty_cache()
     return res
@@ -337,6 +369,7 @@ def bench_c5(steps, warmup):
     import torch
     import synth
     from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd import ops
     from paper_1802_06625_amd.graph import RoutedGraph
     wl = synth.make("C5")
     S, F, n = wl.n_streams, wl.n_frames, int(wl.side[0, 0, 1])
@@ -359,7 +392,8 @@ def bench_c5(steps, warmup):
     res = {"workload": wl.spec.description, "samples": samples,
            "passthrough_frames": int(S * F - n_fb),
            "msamples": round(samples / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
-           "tflops_alg": round(flops / (ms * 1e-3) / 1e12, 2)}
+           "tflops_alg": round(flops / (ms * 1e-3) / 1e12, 2),
+           "fb_variant": ops.variant_names()[ops.autotuned_variant(Lt, wl.Kmax, n) - 1]}
     del g, rg
     torch.cuda.empty_cache()
     return res

@@ -365,6 +365,16 @@ int prune_fb_variant_count(void);
  * PRUNE_AUTOTUNE_CACHE environment variable when set. */
 prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant);
 
+/* Backward form: 0 = automatic (autotuned per shape class like the forward,
+ * cached per process), 1 = vector kernel (Horner form in r), 2 = matrix-core
+ * kernels (block-Toeplitz grad_u and blocked grad_h, Gauss three-product
+ * complex arithmetic).  Both give the same result up to fp32 rounding and
+ * the same deterministic float64 reduction of grad_h. */
+prune_status prune_set_bwd_variant(int variant);
+const char *prune_bwd_variant_name(int variant);
+/* Run the backward autotuner now for (L, K, n) and report the chosen form. */
+prune_status prune_autotune_bwd(uint32_t L, uint32_t K, uint32_t n, int *variant);
+
 /* Device-side timing of the filter-bank kernel launches of the last
  * prune_graph_fire / prune_fb_forward call on this thread (milliseconds,
  * measured with HIP events on the launch stream when timing is on). */

@@ -1,8 +1,9 @@
 """Build libprune_hip.so (HIP for gfx950) in-tree with hipcc.
 
 Every translation unit under csrc/ is compiled as HIP for gfx950 with
-packed-FP32 instructions disabled (-target-feature -packed-fp32-ops), then
-linked into paper_1802_06625_amd/libprune_hip.so.
+packed-FP32 instructions disabled (-target-feature -packed-fp32-ops) and
+matrix-core accumulators selected in VGPR form, then linked into
+paper_1802_06625_amd/libprune_hip.so.
 """
 from __future__ import annotations
 
@@ -23,6 +24,9 @@ ARCH = os.environ.get("PRUNE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs (gfx950 MFMA takes them as
+    # C/D operands): no accumulator copies between AGPRs and VGPRs in loops
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -223,8 +223,9 @@ int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
   }
   const char *env = getenv("PRUNE_AUTOTUNE");
   if (env && env[0] == '0') return 1;
-  // synthetic problem: 4*CUs tiles worth of frames of length nc
-  const uint32_t frames = std::max<uint32_t>(64, (uint32_t)(ncu() * 4 * 2048 / nc));
+  // synthetic problem: 64K samples per CU (16.7M on 256 CUs), long enough
+  // that launch overhead and tail effects do not decide the ranking
+  const uint32_t frames = std::max<uint32_t>(64, (uint32_t)((size_t)ncu() * 65536 / nc));
   const uint64_t N = (uint64_t)frames * nc;
   float2 *x = nullptr, *y = nullptr, *t = nullptr;
   prune_fb_frame *fr = nullptr;

@@ -25,28 +25,25 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <map>
 #include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "prune.h"
 #include "prune_internal.h"
 #include "runtime_kernels.h"
+#include "bwd_common.h"
 
 namespace prune {
 
 constexpr int kBJ = 4;          // inputs per lane for grad_x
 constexpr int kBWG = 256;
-constexpr int kBT = kBJ * kBWG;  // tile
+static_assert(kBJ * kBWG == kBT, "vector backward tile");
 constexpr int kRedChunk = 64;    // tiles per first-stage reduction chunk
 constexpr int kRedG = 64;        // chunk groups per stream
-
-struct BwdFrame {
-  const float2 *x;      // sample 0 of the frame (stream pointer + t0)
-  const float2 *g;      // cotangent at sample 0
-  float2 *gx;           // grad_x at sample 0
-  const float2 *taps;   // [n_banks][Kmax][Lmax] of the frame's stream
-  uint32_t n, mask, route, t0;
-  uint32_t stream, pad0, pad1, pad2;
-};
 
 __device__ __forceinline__ int bidx(int i) { return i + (i >> 3); }
 
@@ -262,6 +259,7 @@ __global__ __launch_bounds__(kBWG) void k_bwd_main(prune_fb_desc d, const BwdFra
         for (int b = 0; b < 10; ++b) ar[b] = ai[b] = 0.f;
         if (ch < nch) {
           const int hi = min(kBT, (ch + 1) * per);
+#pragma unroll 4
           for (int k = ch * per; k < hi; ++k) {
             const float2 gv = gw[bidx(k)];
             const float4 xv = xw[bidx(k - l + Lpad - 1)];
@@ -330,6 +328,11 @@ __global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const int H = (int)Lmax - 1;
   const int k = threadIdx.x;
+  __shared__ float2 tl[PRUNE_MAX_BRANCHES * PRUNE_MAX_L];
+  const uint32_t E = d.n_banks * d.Kmax * Lmax;
+  if (!F.route && F.n)
+    for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) tl[e] = F.taps[e];
+  __syncthreads();
   if (k >= H) return;
   const int m = k - H;                     // position relative to the frame start
   float2 out = make_float2(0.f, 0.f);
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame
       if (!bmask) continue;
       const int KH = 32 - __clz(bmask);
       const int L = (int)d.L[bank];
-      const float2 *tb = F.taps + (size_t)bank * d.Kmax * Lmax;
+      const float2 *tb = tl + (size_t)bank * d.Kmax * Lmax;
       for (int l = -m; l < L && m + l < (int)F.n; ++l) {
         float qr = 0.f, qi = 0.f, tr = 0.f, ti = 0.f;
         for (int b = KH - 1; b >= 0; --b) {
@@ -415,16 +418,26 @@ __global__ __launch_bounds__(256) void k_bwd_reduce1(prune_fb_desc d, const floa
   const uint32_t b0 = s_begin[s], b1 = s_end[s];
   const uint32_t nch = (b1 - b0 + kRedChunk - 1) / kRedChunk;
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
-    double sr = 0.0, si = 0.0;
+    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
     for (uint32_t c = grp; c < nch; c += gridDim.y) {
       const uint32_t lo = b0 + c * kRedChunk, hi = min(b1, lo + kRedChunk);
-      for (uint32_t t = lo; t < hi; ++t) {
+      uint32_t t = lo;
+      for (; t + 4 <= hi; t += 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float2 v = partial[(size_t)(t + q) * E + e];
+          sr[q] += v.x;
+          si[q] += v.y;
+        }
+      }
+      for (; t < hi; ++t) {
         const float2 v = partial[(size_t)t * E + e];
-        sr += v.x;
-        si += v.y;
+        sr[0] += v.x;
+        si[0] += v.y;
       }
     }
-    part2[((size_t)s * gridDim.y + grp) * E + e] = make_double2(sr, si);
+    part2[((size_t)s * gridDim.y + grp) * E + e] =
+        make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
   }
 }
 
@@ -435,13 +448,19 @@ __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const doub
   const uint32_t E = d.n_banks * d.Kmax * Lmax;
   const uint32_t s = blockIdx.x;
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
-    double sr = 0.0, si = 0.0;
-    for (uint32_t g = 0; g < groups; ++g) {
-      const double2 v = part2[((size_t)s * groups + g) * E + e];
-      sr += v.x;
-      si += v.y;
+    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t g = 0; g < groups; g += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (g + q < groups) {
+          const double2 v = part2[((size_t)s * groups + g + q) * E + e];
+          sr[q] += v.x;
+          si[q] += v.y;
+        }
+      }
     }
-    gtaps[(size_t)s * E + e] = make_float2((float)sr, (float)si);
+    gtaps[(size_t)s * E + e] = make_float2((float)((sr[0] + sr[1]) + (sr[2] + sr[3])),
+                                           (float)((si[0] + si[1]) + (si[2] + si[3])));
   }
 }
 
@@ -481,6 +500,16 @@ static prune_status check_bwd_desc(const prune_fb_desc *d) {
   return PRUNE_OK;
 }
 
+constexpr int kBwdVariants = 2;   // 1: vector Horner kernel, 2: matrix-core kernels
+static std::atomic<int> g_bwd_forced{0};
+static std::mutex g_bwd_mu;
+static std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int> g_bwd_tuned;
+static int choose_bwd_variant(uint32_t L, uint32_t K, uint32_t n);
+static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x, const void *taps,
+                                        const void *frames, const void *gy, void *gx, void *gtaps,
+                                        void *workspace, size_t workspace_bytes, int variant,
+                                        prune_stream_t stream);
+
 }  // namespace prune
 
 using namespace prune;
@@ -500,6 +529,42 @@ prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const v
                                void *workspace, size_t workspace_bytes, prune_stream_t stream) {
   prune_status st = check_bwd_desc(desc);
   if (st != PRUNE_OK) return st;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
+  const int v = choose_bwd_variant(Lmax, desc->Kmax, desc->max_frame_len);
+  return fb_backward_variant(desc, x, taps, frames, gy, gx, gtaps, workspace, workspace_bytes, v,
+                             stream);
+}
+
+prune_status prune_set_bwd_variant(int variant) {
+  if (variant < 0 || variant > kBwdVariants) return PRUNE_E_ARG;
+  g_bwd_forced.store(variant);
+  return PRUNE_OK;
+}
+
+const char *prune_bwd_variant_name(int variant) {
+  switch (variant) {
+    case 1: return "valu_horner";
+    case 2: return "mfma_toeplitz";
+    default: return "auto";
+  }
+}
+
+prune_status prune_autotune_bwd(uint32_t L, uint32_t K, uint32_t n, int *variant) {
+  if (L < 1 || L > PRUNE_MAX_L || K < 1 || K > 10 || n < 1) return PRUNE_E_ARG;
+  const int v = choose_bwd_variant(L, K, n);
+  if (variant) *variant = v;
+  return PRUNE_OK;
+}
+
+}  // extern "C"
+
+namespace prune {
+
+static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x, const void *taps,
+                                        const void *frames, const void *gy, void *gx, void *gtaps,
+                                        void *workspace, size_t workspace_bytes, int variant,
+                                        prune_stream_t stream) {
   if (!x || !taps || !frames || !gy || !gx || !gtaps || !workspace) return PRUNE_E_ARG;
   const BwdLayout L = bwd_layout(*desc);
   if (workspace_bytes < L.total) return PRUNE_E_CAPACITY;
@@ -528,7 +593,12 @@ prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const v
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
-  hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
+  if (variant == 2) {
+    launch_bwd_gu_mfma(d, bf, items, cnt, grid, s);
+    launch_bwd_gh_mfma(d, bf, items, cnt, partial, grid, s);
+  } else {
+    hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
+  }
   if (L.H) {
     hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
     hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
@@ -540,4 +610,86 @@ prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const v
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }
 
-}  // extern "C"
+// Time both backward forms on a synthetic batch of the shape class and keep
+// the faster.  Key: (L rounded up to a multiple of 8, K, frame length class).
+static int choose_bwd_variant(uint32_t L, uint32_t K, uint32_t n) {
+  const int forced = g_bwd_forced.load();
+  if (forced) return forced;
+  const uint32_t Lc = (L + 7) / 8 * 8;
+  const uint32_t nc = n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512);
+  const auto key = std::make_tuple(Lc, K, nc);
+  {
+    std::lock_guard<std::mutex> lk(g_bwd_mu);
+    auto it = g_bwd_tuned.find(key);
+    if (it != g_bwd_tuned.end()) return it->second;
+  }
+  const char *env = getenv("PRUNE_AUTOTUNE");
+  if (env && env[0] == '0') return 1;
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t frames = std::max<uint32_t>(64, (uint32_t)((size_t)ncu * 16384 / nc));
+  const uint64_t N = (uint64_t)frames * nc;
+  prune_fb_desc d{};
+  d.n_streams = 1; d.n_frames = frames; d.stream_len = N; d.n_banks = 1; d.Kmax = K;
+  d.L[0] = Lc; d.max_frame_len = nc;
+  const size_t ws = bwd_layout(d).total;
+  float2 *x = nullptr, *g = nullptr, *gx = nullptr, *t = nullptr, *gt = nullptr;
+  prune_fb_frame *fr = nullptr;
+  void *work = nullptr;
+  int best = 1;
+  bool ok = hipMalloc((void **)&x, N * sizeof(float2)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&g, N * sizeof(float2)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&gx, N * sizeof(float2)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&t, (size_t)K * Lc * sizeof(float2)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&gt, (size_t)K * Lc * sizeof(float2)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&fr, frames * sizeof(prune_fb_frame)) == hipSuccess;
+  ok = ok && hipMalloc(&work, ws) == hipSuccess;
+  if (ok) {
+    std::vector<float2> hx(N);
+    uint32_t st = 2468u;
+    for (auto &v : hx) {
+      st = st * 1664525u + 1013904223u;
+      v.x = ((st >> 8) & 0xffff) / 65536.f - 0.5f;
+      st = st * 1664525u + 1013904223u;
+      v.y = ((st >> 8) & 0xffff) / 65536.f - 0.5f;
+    }
+    (void)hipMemcpy(x, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice);
+    (void)hipMemcpy(g, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice);
+    std::vector<float2> ht((size_t)K * Lc, make_float2(0.01f, -0.02f));
+    (void)hipMemcpy(t, ht.data(), ht.size() * sizeof(float2), hipMemcpyHostToDevice);
+    std::vector<prune_fb_frame> hf(frames);
+    for (uint32_t f = 0; f < frames; ++f) {
+      hf[f].stream = 0; hf[f].t0 = f * nc; hf[f].n = nc;
+      hf[f].mask = (1u << K) - 1u; hf[f].route = 0;
+      hf[f].pad[0] = hf[f].pad[1] = hf[f].pad[2] = 0;
+    }
+    (void)hipMemcpy(fr, hf.data(), frames * sizeof(prune_fb_frame), hipMemcpyHostToDevice);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    for (int v = 1; v <= kBwdVariants; ++v) {
+      fb_backward_variant(&d, x, t, fr, g, gx, gt, work, ws, v, nullptr);   // warm-up
+      (void)hipEventRecord(e0, nullptr);
+      for (int r = 0; r < 3; ++r) fb_backward_variant(&d, x, t, fr, g, gx, gt, work, ws, v, nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  (void)hipFree(x); (void)hipFree(g); (void)hipFree(gx); (void)hipFree(t); (void)hipFree(gt);
+  (void)hipFree(fr); (void)hipFree(work);
+  std::lock_guard<std::mutex> lk(g_bwd_mu);
+  g_bwd_tuned[key] = best;
+  return best;
+}
+
+}  // namespace prune

@@ -22,6 +22,7 @@
 // of 2J-1 samples per chunk of J taps; the tap coefficients of the chunk are
 // LDS broadcasts.
 #include "prune_internal.h"
+#include "runtime_kernels.h"
 
 namespace prune {
 
@@ -174,7 +175,7 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
 // ---------------------------------------------------------------- variants
 struct FbVariant {
   const char *name;
-  int J, WG;
+  int tile, WG;   // outputs per work item, threads per workgroup
   void (*launch)(const FbFrameDesc *, const WorkItem *, const uint32_t *, unsigned int *,
                  uint32_t grid, hipStream_t);
 };
@@ -186,18 +187,22 @@ static void launch_fwd(const FbFrameDesc *f, const WorkItem *it, const uint32_t 
 }
 
 static const FbVariant kVariants[] = {
-    {"valu_horner_J8_WG256_w2", 8, 256, launch_fwd<8, 256, 2>},
-    {"valu_horner_J4_WG256_w3", 4, 256, launch_fwd<4, 256, 3>},
-    {"valu_horner_J8_WG128_w2", 8, 128, launch_fwd<8, 128, 2>},
-    {"valu_horner_J4_WG128_w4", 4, 128, launch_fwd<4, 128, 4>},
-    {"valu_horner_J8_WG256_w1", 8, 256, launch_fwd<8, 256, 1>},
+    {"valu_horner_J8_WG256_w2", 8 * 256, 256, launch_fwd<8, 256, 2>},
+    {"valu_horner_J4_WG256_w3", 4 * 256, 256, launch_fwd<4, 256, 3>},
+    {"valu_horner_J8_WG128_w2", 8 * 128, 128, launch_fwd<8, 128, 2>},
+    {"valu_horner_J4_WG128_w4", 4 * 128, 128, launch_fwd<4, 128, 4>},
+    {"valu_horner_J8_WG256_w1", 8 * 256, 256, launch_fwd<8, 256, 1>},
+    // matrix-core block-Toeplitz kernels: NT result tiles per wave, NW waves
+    {"mfma_toeplitz_NT4_W4", 4 * 256 * 4, 256, launch_fb_mfma<4, 4>},
+    {"mfma_toeplitz_NT2_W4", 2 * 256 * 4, 256, launch_fb_mfma<2, 4>},
+    {"mfma_toeplitz_NT4_W2", 4 * 256 * 2, 128, launch_fb_mfma<4, 2>},
 };
 
 int fb_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const char *fb_variant_name(int v) {
   return (v >= 1 && v <= fb_variant_count()) ? kVariants[v - 1].name : "auto";
 }
-int fb_variant_tile(int v) { return kVariants[v - 1].J * kVariants[v - 1].WG; }
+int fb_variant_tile(int v) { return kVariants[v - 1].tile; }
 int fb_variant_wg(int v) { return kVariants[v - 1].WG; }
 
 void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,

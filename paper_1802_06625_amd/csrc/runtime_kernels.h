@@ -87,6 +87,9 @@ void launch_gather(const CtrlArgs &c, uint32_t level, uint32_t grid, hipStream_t
 void launch_clear(uint32_t *p, uint32_t n, hipStream_t s);
 void launch_copyback(const CtrlArgs &c, uint32_t a, uint32_t fifo, uint32_t k, hipStream_t s);
 
+template <int NT, int NW>
+void launch_fb_mfma(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
+                    unsigned int *ticket, uint32_t grid, hipStream_t s);
 int fb_variant_count();
 const char *fb_variant_name(int v);
 int fb_variant_tile(int v);

@@ -143,6 +143,21 @@ def autotuned_variant(L, K, n):
     return v.value
 
 
+def set_bwd_variant(v):
+    """0: autotuned, 1: vector kernel, 2: matrix-core kernels."""
+    call("prune_set_bwd_variant", int(v))
+
+
+def bwd_variant_name(v):
+    return L.lib().prune_bwd_variant_name(int(v)).decode()
+
+
+def autotuned_bwd_variant(L_, K, n):
+    v = C.c_int()
+    call("prune_autotune_bwd", int(L_), int(K), int(n), C.byref(v))
+    return v.value
+
+
 def timing_enable(on=True):
     call("prune_timing_enable", int(on))
 

@@ -26,17 +26,34 @@ def _rows(wl):
     return [(s, t0, n, m, r) for s in range(wl.n_streams) for (t0, n, m, r) in stream_frames(wl, s)]
 
 
+BWD_FORMS = [1, 2]      # 1: vector kernel, 2: matrix-core kernels
+
+
+def _backward(x, t, fr, gy, Kmax, bank_L, mfl, form):
+    ops.set_bwd_variant(form)
+    try:
+        gx, gt = ops.fb_backward(x, t, fr, gy, Kmax, bank_L, mfl)
+        torch.cuda.synchronize()
+        return gx.cpu().numpy(), gt.cpu().numpy()
+    finally:
+        ops.set_bwd_variant(0)
+
+
+def test_bwd_variant_names():
+    assert [ops.bwd_variant_name(v) for v in (0, 1, 2)] == ["auto", "valu_horner", "mfma_toeplitz"]
+
+
+@pytest.mark.parametrize("form", BWD_FORMS)
 @pytest.mark.parametrize("name", ["C1", "C3", "C4", "C5"])
-def test_backward_parity(name):
-    announce(f"backward {name}")
+def test_backward_parity(name, form):
+    announce(f"backward {name} form {form}")
     wl = synth.scaled(name, cotangent=True) if name != "C1" else synth.make("C1", cotangent=True)
     rows = _rows(wl)
     fr = ops.frame_table(rows)
     x = torch.from_numpy(wl.x).cuda()
     t = torch.from_numpy(wl.taps).cuda()
     gy = torch.from_numpy(wl.gy).cuda()
-    gx, gt = ops.fb_backward(x, t, fr, gy, wl.Kmax, wl.bank_L, int(wl.side[:, :, 1].max()))
-    gx, gt = gx.cpu().numpy(), gt.cpu().numpy()
+    gx, gt = _backward(x, t, fr, gy, wl.Kmax, wl.bank_L, int(wl.side[:, :, 1].max()), form)
     for s in range(wl.n_streams):
         rx, rt = fb_stream_adjoint(wl.x[s], stream_frames(wl, s), wl.taps[s], wl.bank_L, wl.Kmax,
                                    wl.gy[s])
@@ -47,9 +64,10 @@ def test_backward_parity(name):
             assert np.all(gt[s, b, :, L:] == 0)
 
 
-def test_backward_edge_frames():
+@pytest.mark.parametrize("form", BWD_FORMS)
+def test_backward_edge_frames(form):
     """Short frames (< L-1), empty masks, passthrough frames, several banks."""
-    announce("backward edge frames")
+    announce(f"backward edge frames form {form}")
     wl = synth.make("C3", n_frames=10, n_max=300, cotangent=True)
     lens = [3, 50, 7, 300, 1, 31, 2, 129, 64, 11]
     N = sum(lens)
@@ -61,12 +79,38 @@ def test_backward_edge_frames():
         rows.append((0, t0, n, m, r))
         t0 += n
     fr = ops.frame_table(rows)
-    gx, gt = ops.fb_backward(torch.from_numpy(wl.x).cuda(), torch.from_numpy(wl.taps).cuda(), fr,
-                             torch.from_numpy(wl.gy).cuda(), wl.Kmax, wl.bank_L, max(lens))
+    gx, gt = _backward(torch.from_numpy(wl.x).cuda(), torch.from_numpy(wl.taps).cuda(), fr,
+                       torch.from_numpy(wl.gy).cuda(), wl.Kmax, wl.bank_L, max(lens), form)
     ref = [(t, n, m, r) for (_, t, n, m, r) in rows]
     rx, rt = fb_stream_adjoint(wl.x[0], ref, wl.taps[0], wl.bank_L, wl.Kmax, wl.gy[0])
-    assert rel_l2(gx.cpu().numpy()[0], rx) <= TOL
-    assert rel_l2(gt.cpu().numpy()[0], rt) <= TOL
+    assert rel_l2(gx[0], rx) <= TOL
+    assert rel_l2(gt[0], rt) <= TOL
+
+
+@pytest.mark.parametrize("L", [1, 5, 16, 17, 33, 63, 64])
+def test_backward_forms_agree_across_tap_counts(L):
+    """Both backward forms against the oracle at tap counts around the
+    matrix kernels' step (4) and slab (16) sizes, all ten branches, frames
+    ending inside a tile, and a frame shorter than the filter."""
+    announce(f"backward forms L={L}")
+    wl = synth.make("C4", n_frames=5, frame_len=3000, cotangent=True)
+    rng = np.random.default_rng(100 + L)
+    taps = (rng.standard_normal((1, 1, 10, L)) + 1j * rng.standard_normal((1, 1, 10, L))
+            ).astype(np.complex64) / (4 * L)
+    lens = [3000, 2, 2500, 1030, 7000 - 5032]
+    rows, t0 = [], 0
+    for n, m in zip(lens, [0x3FF, 0x3FF, 0x155, 1, 0x2AA]):
+        rows.append((0, t0, n, m, 0))
+        t0 += n
+    x, gy = wl.x[:, :t0].copy(), wl.gy[:, :t0].copy()
+    rx, rt = fb_stream_adjoint(x[0], [(a, n, m, r) for (_, a, n, m, r) in rows], taps[0], (L,), 10,
+                               gy[0])
+    for form in BWD_FORMS:
+        gx, gt = _backward(torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(),
+                           ops.frame_table(rows), torch.from_numpy(gy).cuda(), 10, (L,), max(lens),
+                           form)
+        assert rel_l2(gx[0], rx) <= TOL, (form, rel_l2(gx[0], rx))
+        assert rel_l2(gt[0], rt) <= TOL, (form, rel_l2(gt[0], rt))
 
 
 def test_autograd_function_matches_oracle():

@@ -58,18 +58,60 @@ def test_forward_parity_scaled(name):
         assert rel_l2(y[s], ref[s]) <= TOL, (name, s, rel_l2(y[s], ref[s]))
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
-def test_every_variant(variant):
-    announce(f"forward variant {variant}")
-    wl = synth.scaled("C3")
+N_VARIANTS = 8          # 1-5 vector Horner kernels, 6-8 matrix-core block-Toeplitz
+MFMA_VARIANTS = [6, 7, 8]
+
+
+def test_variant_names():
+    names = ops.variant_names()
+    assert len(names) == N_VARIANTS
+    assert all(names[v - 1].startswith("mfma") for v in MFMA_VARIANTS)
+
+
+@pytest.mark.parametrize("name", ["C3", "C5"])
+@pytest.mark.parametrize("variant", list(range(1, N_VARIANTS + 1)))
+def test_every_variant(variant, name):
+    """Three banks of L = 8/16/32 with log-uniform frame lengths (C3), and
+    L = 64 over routed multi-stream frames (C5)."""
+    announce(f"forward variant {variant} {name}")
+    wl = synth.scaled(name)
     y, _ = _device_forward(wl, variant)
-    assert rel_l2(y[0], _oracle(wl)[0]) <= TOL
+    ref = _oracle(wl)
+    for s in range(wl.n_streams):
+        assert rel_l2(y[s], ref[s]) <= TOL, (s, rel_l2(y[s], ref[s]))
 
 
-def test_forward_edge_frames():
+@pytest.mark.parametrize("L", [1, 5, 17, 63, 64])
+@pytest.mark.parametrize("variant", MFMA_VARIANTS)
+def test_mfma_tap_counts(variant, L):
+    """Block-Toeplitz kernels at tap counts that are not multiples of the
+    step of 4, with every branch, and frames that end inside a tile."""
+    announce(f"mfma variant {variant} L={L}")
+    wl = synth.make("C4", n_frames=6, frame_len=5000)
+    rng = np.random.default_rng(L)
+    taps = (rng.standard_normal((1, 1, 10, L)) + 1j * rng.standard_normal((1, 1, 10, L))
+            ).astype(np.complex64) / (4 * L)
+    lens = [5000, 1, 4500, 9000 - 4501, 700, 3000]
+    rows, t0 = [], 0
+    for n, m in zip(lens, [0x3FF, 0x3FF, 0x155, 1, 0x3FF, 0x2AA]):
+        rows.append((0, t0, n, m, 0))
+        t0 += n
+    x = wl.x[:, :t0].copy()
+    ops.set_variant(variant)
+    try:
+        y = ops.fb_forward(torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(),
+                           ops.frame_table(rows), 10, (L,), max(lens)).cpu().numpy()
+    finally:
+        ops.set_variant(0)
+    ref = fb_stream(x[0], [(a, n, m, r) for (_, a, n, m, r) in rows], taps[0], (L,), 10)
+    assert rel_l2(y[0], ref) <= TOL, rel_l2(y[0], ref)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 6, 8])
+def test_forward_edge_frames(variant):
     """Empty-mask frames, frames of 1 sample, frames shorter than the filter,
     passthrough frames, and masks mixing two banks."""
-    announce("forward edge frames")
+    announce(f"forward edge frames variant {variant}")
     wl = synth.make("C3", n_frames=12, n_max=300)
     lens = [1, 3, 50, 7, 300, 1, 31, 2, 129, 64, 5, 11]
     N = sum(lens)
@@ -83,7 +125,11 @@ def test_forward_edge_frames():
     fr = ops.frame_table(rows)
     x = torch.from_numpy(wl.x).cuda()
     taps = torch.from_numpy(wl.taps).cuda()
-    y = ops.fb_forward(x, taps, fr, wl.Kmax, wl.bank_L, max(lens)).cpu().numpy()
+    ops.set_variant(variant)
+    try:
+        y = ops.fb_forward(x, taps, fr, wl.Kmax, wl.bank_L, max(lens)).cpu().numpy()
+    finally:
+        ops.set_variant(0)
     ref = fb_stream(wl.x[0], [(t0, n, m, r) for (_, t0, n, m, r) in rows], wl.taps[0], wl.bank_L,
                     wl.Kmax)
     assert rel_l2(y[0], ref) <= TOL
@@ -110,3 +156,29 @@ def test_full_size_c2_sampled_frames():
         win = np.concatenate([np.zeros(H - len(past), np.complex64), past, x[t0:t0 + n]])
         ref = fb_frame(win, H, wl.taps[0], wl.bank_L, wl.Kmax, m)
         assert rel_l2(y[0, t0:t0 + n], ref) <= TOL, f
+
+
+def _sampled_frames(wl, y, rows, k, seed=0):
+    H = max(wl.bank_L) - 1
+    rng = np.random.default_rng(seed)
+    for f in sorted(rng.choice(len(rows), k, replace=False).tolist() + [0, len(rows) - 1]):
+        s_, t0, n, m, r = rows[f]
+        x = wl.x[s_]
+        if r:
+            np.testing.assert_array_equal(y[s_, t0:t0 + n], x[t0:t0 + n])
+            continue
+        past = x[max(0, t0 - H):t0]
+        win = np.concatenate([np.zeros(H - len(past), np.complex64), past, x[t0:t0 + n]])
+        ref = fb_frame(win, H, wl.taps[s_], wl.bank_L, wl.Kmax, m)
+        assert rel_l2(y[s_, t0:t0 + n], ref) <= TOL, (f, rel_l2(y[s_, t0:t0 + n], ref))
+
+
+@pytest.mark.parametrize("variant", [0, 6])
+def test_full_size_c5_sampled_frames(variant):
+    """C5 at full size (64 streams x 16 x 32768, K=7, L=64, routed frames) in
+    the launch configuration of the measured run: sampled frames against the
+    oracle, frame by frame."""
+    announce(f"full-size C5 sampled frames variant {variant}")
+    wl = synth.make("C5")
+    y, rows = _device_forward(wl, variant)
+    _sampled_frames(wl, y, rows, 8)

@@ -169,3 +169,22 @@ def test_delay_fifo_per_firing(r, Q, C):
     for fid in (0, 1):
         assert fifos[fid]["writes"] == [tuple(w) for w in logs["fifos"][fid]["writes"]]
         assert fifos[fid]["reads"] == [tuple(w) for w in logs["fifos"][fid]["reads"]]
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED_GRAPH])
+def test_routed_multistream_mfma(mode):
+    """The routed graph with the filter bank on the matrix-core kernel (tiles
+    of 4096 outputs, larger than a scaled frame)."""
+    announce(f"routed C5-scaled mfma mode={mode}")
+    from paper_1802_06625_amd import ops
+    wl = synth.scaled("C5")
+    y_ref, logs_ref, _, ids = og.run_routed(wl, C=5)
+    ops.set_variant(6)
+    try:
+        dev = run_routed_device(wl, 5, mode)
+    finally:
+        ops.set_variant(0)
+    for s in range(wl.n_streams):
+        assert rel_l2(dev["y"][s], y_ref[s]) <= TOL, s
+    compare_logs(dev, logs_ref, [i["sw"] for i in ids] + [i["sel"] for i in ids])
+    compare_stats(dev["g"], logs_ref)
