@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 flop x 2.4 GHz
+PEAK_FP32_MATRIX_TFLOPS = 157.3     # 256 CU x 4 SIMD x 2048 flop per 32-cycle 16x16x4 MFMA x 2.4 GHz
 PEAK_HBM_GBPS = 8000.0
 METRIC = "actor Msamples/s fwd and fwd+bwd, batched vs per-frame, at ≤2e-5 rel err"
 
@@ -318,6 +319,29 @@ def bench_direct(name, steps, warmup):
         res["fwd_ms_by_variant"] = by_variant
         res["fwd_tflops_alg_by_variant"] = {k: round(f_fwd / (v * 1e-3) / 1e12, 2)
                                             for k, v in by_variant.items()}
+        # matrix-core kernel (block-Toeplitz form): the fastest of its
+        # variants, kernel duration from the library's HIP events on the
+        # launch stream
+        names = ops.variant_names()
+        mv = min((k for k in by_variant if k.startswith("mfma")), key=by_variant.get)
+        ops.set_variant(names.index(mv) + 1)
+        ops.timing_enable(True)
+        try:
+            kms = []
+            for _ in range(5):
+                fwd()
+                torch.cuda.synchronize()
+                ms, nl = ops.last_fb_kernel_ms()
+                kms.append(ms / max(nl, 1))
+        finally:
+            ops.timing_enable(False)
+            ops.set_variant(0)
+        k_ms = float(np.mean(kms))
+        ach = f_fwd / (k_ms * 1e-3) / 1e12
+        res["roofline_mfma"] = {"bound": "mfma", "kernel": "k_fb_mfma", "variant": mv,
+                                "achieved": round(ach, 2), "peak": PEAK_FP32_MATRIX_TFLOPS,
+                                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_MATRIX_TFLOPS, 4),
+                                "kernel_ms": round(k_ms, 4), "algorithmic_flops_per_launch": f_fwd}
     del x, taps, gy, y, gx, gt, work
     torch.cuda.empty_cache()
     return res

@@ -178,7 +178,19 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
   launch_direct_prep(*desc, (const float2 *)x, (const float2 *)taps, (const prune_fb_frame *)frames,
                      (float2 *)y, tile, sc->desc, sc->items, sc->ctr, sc->ctr + 1, sc->ctr + 2, s);
   const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 3, items);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = timing_on();
+  if (timed) {
+    timing_restart();
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, s);
+  }
   fb_forward_launch(variant, sc->desc, sc->items, sc->ctr, (unsigned int *)(sc->ctr + 1), grid, s);
+  if (timed) {
+    (void)hipEventRecord(e1, s);
+    timing_push(e0, e1);
+  }
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }
 }  // namespace prune

@@ -42,8 +42,7 @@ namespace prune {
 constexpr int kBJ = 4;          // inputs per lane for grad_x
 constexpr int kBWG = 256;
 static_assert(kBJ * kBWG == kBT, "vector backward tile");
-constexpr int kRedChunk = 64;    // tiles per first-stage reduction chunk
-constexpr int kRedG = 64;        // chunk groups per stream
+constexpr int kRedG = 64;        // first-stage chunks per stream
 
 __device__ __forceinline__ int bidx(int i) { return i + (i >> 3); }
 
@@ -329,9 +328,13 @@ __global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame
   const int H = (int)Lmax - 1;
   const int k = threadIdx.x;
   __shared__ float2 tl[PRUNE_MAX_BRANCHES * PRUNE_MAX_L];
+  __shared__ float2 gl[PRUNE_MAX_L];       // the frame's first H outputs' cotangent
   const uint32_t E = d.n_banks * d.Kmax * Lmax;
-  if (!F.route && F.n)
+  if (!F.route && F.n) {
     for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) tl[e] = F.taps[e];
+    for (int e = threadIdx.x; e < H; e += blockDim.x)
+      gl[e] = e < (int)F.n ? F.g[e] : make_float2(0.f, 0.f);
+  }
   __syncthreads();
   if (k >= H) return;
   const int m = k - H;                     // position relative to the frame start
@@ -358,7 +361,7 @@ __global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame
           tr = fmaf(tr, r, be * h.x);
           ti = fmaf(ti, r, be * h.y);
         }
-        const float2 gv = F.g[m + l];
+        const float2 gv = gl[m + l];
         s1r += gv.x * qr - gv.y * qi;
         s1i += gv.x * qi + gv.y * qr;
         s2r += gv.x * tr + gv.y * ti;
@@ -407,60 +410,73 @@ __global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_
   F.gx[local] = acc;
 }
 
+// Two-stage fixed-order float64 reduction of the tile partials of each
+// stream.  Stage 1: workgroup (stream s, block of 64 entries, chunk c) sums
+// the stream's tiles of chunk c; its 4 x 64 threads take tiles q, q+4, ... of
+// the chunk and their sums are added in q order.  Stage 2: workgroup
+// (s, entry block) adds the chunk sums the same way.  The order of every sum
+// depends only on the item list, so results are reproducible.
+constexpr int kRedQ = 4;          // sub-sums per entry
 __global__ __launch_bounds__(256) void k_bwd_reduce1(prune_fb_desc d, const float2 *__restrict__ partial,
                                                      const uint32_t *__restrict__ s_begin,
                                                      const uint32_t *__restrict__ s_end,
                                                      double2 *__restrict__ part2) {
+  __shared__ double2 red[kRedQ][64];
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const uint32_t E = d.n_banks * d.Kmax * Lmax;
-  const uint32_t s = blockIdx.x, grp = blockIdx.y;
+  const uint32_t s = blockIdx.x, eb = blockIdx.y, c = blockIdx.z;
+  const uint32_t el = threadIdx.x & 63, q = threadIdx.x >> 6, e = eb * 64 + el;
   const uint32_t b0 = s_begin[s], b1 = s_end[s];
-  const uint32_t nch = (b1 - b0 + kRedChunk - 1) / kRedChunk;
-  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
-    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
-    for (uint32_t c = grp; c < nch; c += gridDim.y) {
-      const uint32_t lo = b0 + c * kRedChunk, hi = min(b1, lo + kRedChunk);
-      uint32_t t = lo;
-      for (; t + 4 <= hi; t += 4) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float2 v = partial[(size_t)(t + q) * E + e];
-          sr[q] += v.x;
-          si[q] += v.y;
-        }
-      }
-      for (; t < hi; ++t) {
-        const float2 v = partial[(size_t)t * E + e];
-        sr[0] += v.x;
-        si[0] += v.y;
-      }
+  const uint32_t per = (b1 - b0 + kRedG - 1) / kRedG;
+  const uint32_t lo = min(b1, b0 + c * per), hi = min(b1, lo + per);
+  double sr = 0.0, si = 0.0;
+  if (e < E) {
+    for (uint32_t t = lo + q; t < hi; t += kRedQ) {
+      const float2 v = partial[(size_t)t * E + e];
+      sr += v.x;
+      si += v.y;
     }
-    part2[((size_t)s * gridDim.y + grp) * E + e] =
-        make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
+  }
+  red[q][el] = make_double2(sr, si);
+  __syncthreads();
+  if (q == 0 && e < E) {
+    double2 a = red[0][el];
+#pragma unroll
+    for (int k = 1; k < kRedQ; ++k) {
+      a.x += red[k][el].x;
+      a.y += red[k][el].y;
+    }
+    part2[((size_t)s * kRedG + c) * E + e] = a;
   }
 }
 
 __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const double2 *__restrict__ part2,
-                                                     uint32_t groups, float2 *__restrict__ gtaps) {
+                                                     float2 *__restrict__ gtaps) {
+  __shared__ double2 red[kRedQ][64];
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const uint32_t E = d.n_banks * d.Kmax * Lmax;
-  const uint32_t s = blockIdx.x;
-  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
-    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
-    for (uint32_t g = 0; g < groups; g += 4) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (g + q < groups) {
-          const double2 v = part2[((size_t)s * groups + g + q) * E + e];
-          sr[q] += v.x;
-          si[q] += v.y;
-        }
-      }
+  const uint32_t s = blockIdx.x, eb = blockIdx.y;
+  const uint32_t el = threadIdx.x & 63, q = threadIdx.x >> 6, e = eb * 64 + el;
+  double sr = 0.0, si = 0.0;
+  if (e < E) {
+    for (uint32_t c = q; c < (uint32_t)kRedG; c += kRedQ) {
+      const double2 v = part2[((size_t)s * kRedG + c) * E + e];
+      sr += v.x;
+      si += v.y;
     }
-    gtaps[(size_t)s * E + e] = make_float2((float)((sr[0] + sr[1]) + (sr[2] + sr[3])),
-                                           (float)((si[0] + si[1]) + (si[2] + si[3])));
+  }
+  red[q][el] = make_double2(sr, si);
+  __syncthreads();
+  if (q == 0 && e < E) {
+    double2 a = red[0][el];
+#pragma unroll
+    for (int k = 1; k < kRedQ; ++k) {
+      a.x += red[k][el].x;
+      a.y += red[k][el].y;
+    }
+    gtaps[(size_t)s * E + e] = make_float2((float)a.x, (float)a.y);
   }
 }
 
@@ -604,8 +620,10 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
     hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
                        bf, hg);
   }
-  hipLaunchKernelGGL(k_bwd_reduce1, dim3(d.n_streams, kRedG), dim3(256), 0, s, d, partial, sb, se, part2);
-  hipLaunchKernelGGL(k_bwd_reduce2, dim3(d.n_streams), dim3(256), 0, s, d, part2, (uint32_t)kRedG,
+  const uint32_t eblocks = (L.E + 63) / 64;
+  hipLaunchKernelGGL(k_bwd_reduce1, dim3(d.n_streams, eblocks, kRedG), dim3(256), 0, s, d, partial, sb,
+                     se, part2);
+  hipLaunchKernelGGL(k_bwd_reduce2, dim3(d.n_streams, eblocks), dim3(256), 0, s, d, part2,
                      (float2 *)gtaps);
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }

@@ -34,6 +34,9 @@ int g_variant_forced = 0;
 
 namespace prune {
 int forced_variant() { return g_variant_forced; }
+// Kernel timing of the direct forward (prune_fb_forward) on this thread.
+bool timing_on() { return g_timing; }
+void timing_push(hipEvent_t e0, hipEvent_t e1) { g_events.push_back({e0, e1}); }
 }  // namespace prune
 
 namespace {
@@ -840,6 +843,10 @@ prune_status fire_one(prune_graph *g, uint32_t aid, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace prune {
+void timing_restart() { timing_reset(); }
+}  // namespace prune
 
 // ======================================================================
 // C ABI

@@ -104,6 +104,10 @@ void launch_direct_prep(const prune_fb_desc &d, const float2 *x, const float2 *t
                         FbFrameDesc *desc, WorkItem *items, uint32_t *n_items,
                         unsigned int *ticket, uint32_t *err, hipStream_t s);
 int choose_variant(uint32_t L, uint32_t K, uint32_t n);
+// Per-thread kernel timing (prune_timing_enable / prune_last_fb_kernel_ms).
+bool timing_on();
+void timing_restart();
+void timing_push(hipEvent_t e0, hipEvent_t e1);
 int forced_variant();
 
 }  // namespace prune

@@ -163,3 +163,25 @@ def test_unsupported_shapes():
     with pytest.raises(L.PruneError) as e:
         g.filterbank(4, (65,))
     assert e.value.code == L.E_UNSUPPORTED
+
+
+def test_variant_selection_arguments():
+    """Forward and backward kernel selection: valid indices are accepted,
+    others rejected with E_ARG, and the names are stable."""
+    lib = L.lib()
+    n = lib.prune_fb_variant_count()
+    assert n == 8
+    names = [lib.prune_fb_variant_name(v).decode() for v in range(1, n + 1)]
+    assert all(x.startswith("valu") for x in names[:5]) and all(x.startswith("mfma") for x in names[5:])
+    assert lib.prune_set_fb_variant(n + 1) == L.E_ARG
+    assert lib.prune_set_fb_variant(-1) == L.E_ARG
+    assert lib.prune_set_fb_variant(0) == L.OK
+    assert [lib.prune_bwd_variant_name(v).decode() for v in (0, 1, 2)] == \
+        ["auto", "valu_horner", "mfma_toeplitz"]
+    assert lib.prune_set_bwd_variant(3) == L.E_ARG
+    assert lib.prune_set_bwd_variant(-1) == L.E_ARG
+    for v in (2, 1, 0):
+        assert lib.prune_set_bwd_variant(v) == L.OK
+    v = C.c_int()
+    assert lib.prune_autotune_bwd(0, 7, 1024, C.byref(v)) == L.E_ARG
+    assert lib.prune_autotune_bwd(65, 7, 1024, C.byref(v)) == L.E_ARG
