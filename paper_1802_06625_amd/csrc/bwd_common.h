@@ -24,6 +24,7 @@ struct BwdFrame {
 void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
                         const uint32_t *n_items, uint32_t grid, hipStream_t s);
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
-                        const uint32_t *n_items, float2 *partial, uint32_t grid, hipStream_t s);
+                        const uint32_t *n_items, float2 *partial, uint32_t max_items,
+                        uint32_t grid, hipStream_t s);
 
 }  // namespace prune

@@ -611,7 +611,7 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
   if (variant == 2) {
     launch_bwd_gu_mfma(d, bf, items, cnt, grid, s);
-    launch_bwd_gh_mfma(d, bf, items, cnt, partial, grid, s);
+    launch_bwd_gh_mfma(d, bf, items, cnt, partial, L.max_items, grid, s);
   } else {
     hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
   }

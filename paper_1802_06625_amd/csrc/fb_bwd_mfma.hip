@@ -26,6 +26,8 @@
 //    partials is shared with the vector kernel.
 // Halo contributions (inputs before a frame that its outputs read) are
 // added by the same halo/fix kernels as for the vector form.
+#include <algorithm>
+
 #include "bwd_common.h"
 #include "runtime_kernels.h"
 
@@ -41,7 +43,7 @@ constexpr int kHQ = PRUNE_MAX_L + 36;       // conj-tap table entries per branch
 constexpr int kHOff = 16;                   // table index of tap l = 0
 constexpr int kGB = 4;                      // branches per grad_u pass
 
-__device__ __forceinline__ int widx(int k) { return k + 4 * (k >> 4); }
+__device__ __forceinline__ int widx(int k) { return k + (k >> 4); }
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -56,29 +58,6 @@ __device__ __forceinline__ float ipow(float r, int e) {
     q *= q;
   }
   return p;
-}
-
-// W tiles of branches b0..b0+NB-1 for slab mt over the tile's 64 blocks.
-//  gb: g-window index of A(row li, block lk); xb: x-window index of
-//  B(block lk, column li of slab mt).
-template <int NB>
-__device__ __forceinline__ void gh_unit(const float2 *__restrict__ gw, const float4 *__restrict__ xw,
-                                        int gb, int xb, int b0, floatx4 (&acc)[2][3]) {
-#pragma unroll 2
-  for (int s = 0; s < kBT / 64; ++s) {
-    const float2 gv = gw[gb + 64 * s];
-    const float4 xv = xw[xb + 64 * s];
-    const float gs = gv.x + gv.y;
-    float rp = ipow(xv.z, b0);
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const float ur = xv.x * rp, ui = -(xv.y * rp);   // conj(u_b)
-      acc[j][0] = mfma4(gv.x, ur, acc[j][0]);
-      acc[j][1] = mfma4(gv.y, ui, acc[j][1]);
-      acc[j][2] = mfma4(gs, ur + ui, acc[j][2]);
-      rp *= xv.z;
-    }
-  }
 }
 
 // grad_u of branches b0..b0+NB-1 of one bank for this wave's 16x16 result
@@ -113,7 +92,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
   // G window: index k holds g at tile position k; the last one read is
   // 256*3 + 16*15 + 3 + 4*(S-1) <= kBT + L + 1.
   constexpr int WN = kBT + PRUNE_MAX_L + 2;
-  constexpr int WS = WN + 4 * (WN >> 4) + 4;
+  constexpr int WS = WN + (WN >> 4) + 1;
   __shared__ float2 s_g[WS];
   __shared__ float4 s_h[kMKH * kHQ];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -130,9 +109,20 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
         if (n0 + k < n) F.gx[n0 + k] = F.g[n0 + k];
       continue;
     }
-    for (int k = t; k < WN; k += kWG) {
-      const int q = n0 + k;                  // outputs of this frame only
-      s_g[widx(k)] = q < n ? F.g[q] : make_float2(0.f, 0.f);
+    {
+      // all of this thread's loads first, then the stores (one memory latency)
+      constexpr int NIT = (WN + kWG - 1) / kWG;
+      float2 v[NIT];
+#pragma unroll
+      for (int i = 0; i < NIT; ++i) {
+        const int k = t + i * kWG, q = n0 + k;   // outputs of this frame only
+        v[i] = (k < WN && q < n) ? F.g[q] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < NIT; ++i) {
+        const int k = t + i * kWG;
+        if (k < WN) s_g[widx(k)] = v[i];
+      }
     }
     // this lane's inputs: rows 4lk..4lk+3 of block li of the wave's tile
     const int m0 = n0 + 256 * w + 16 * li + 4 * lk;
@@ -155,11 +145,21 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
       const int S = (L + 15 + 3) / 4;
       __syncthreads();   // s_g written; earlier readers of s_h done
       const float2 *tb = F.taps + (size_t)bank * d.Kmax * Lmax;
-      for (int k = t; k < KH * kHQ; k += kWG) {
-        const int b = k / kHQ, l = k - b * kHQ - kHOff;
-        float2 h = make_float2(0.f, 0.f);
-        if (((bmask >> b) & 1u) && l >= 0 && l < L) h = tb[(size_t)b * Lmax + l];
-        s_h[k] = make_float4(h.x, -h.y, h.x - h.y, 0.f);   // conj(h), Gauss sum
+      {
+        constexpr int NIT = (kMKH * kHQ + kWG - 1) / kWG;
+        float2 hv[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+          const int k = t + i * kWG;
+          const int b = k / kHQ, l = k - b * kHQ - kHOff;
+          hv[i] = (k < KH * kHQ && ((bmask >> b) & 1u) && l >= 0 && l < L) ? tb[(size_t)b * Lmax + l]
+                                                                            : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+          const int k = t + i * kWG;
+          if (k < KH * kHQ) s_h[k] = make_float4(hv[i].x, -hv[i].y, hv[i].x - hv[i].y, 0.f);  // conj(h)
+        }
       }
       __syncthreads();
       // A(row li, m) = Hc[li][m] = conj(h[m - li]);  B(m, block li) = g[16 li + m]
@@ -218,116 +218,190 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
 }
 
 // ------------------------------------------------------------------ grad_h
+namespace {
+constexpr int kGH = 4;                       // branches per staged group
+constexpr int kUMax = 5;                     // units per wave: 5 slabs x 4 branches / 4 waves
+constexpr int kWX = kBT + PRUNE_MAX_L + 16;  // basis-plane positions per tile
+constexpr int kMaxRun = 8;                   // tiles accumulated before the diagonal sums
+
+// One unit's contribution of one tile: 16 steps of 4 blocks.
+//  gb: g-plane index of A(row li, block lk); ub: u-plane index of
+//  B(block lk, column li of the unit's slab).
+__device__ __forceinline__ void gh_tile(const float4 *__restrict__ gp, const float2 *__restrict__ up,
+                                        int gb, int ub, floatx4 (&acc)[3]) {
+#pragma unroll
+  for (int s = 0; s < kBT / 64; ++s) {
+    const float4 gv = gp[gb + 64 * s];
+    const float2 uv = up[ub + 64 * s];
+    acc[0] = mfma4(gv.x, uv.x, acc[0]);
+    acc[1] = mfma4(gv.y, uv.y, acc[1]);
+    acc[2] = mfma4(gv.z, uv.x + uv.y, acc[2]);
+  }
+}
+}  // namespace
+
+// grad_h partials.  Work: runs of up to `run` consecutive tiles of one frame
+// (item groups [g*run, g*run+run) split where the frame changes).  A run's
+// W tiles are accumulated over all its tiles, then reduced once; the sum is
+// the partial row of the run's first item and the other items' rows are
+// zero.  Per tile and group of up to four branches, LDS holds the cotangent
+// as {gr, gi, gr+gi} and the planes conj(u_b) = {ur, -ui} of the group's
+// branches over the tile's window.
 __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdFrame *__restrict__ bf,
                                                     const WorkItem *__restrict__ items,
                                                     const uint32_t *__restrict__ n_items,
-                                                    float2 *__restrict__ partial) {
-  // X window: index k holds x at tile position k - (Lmax-1); the last one
-  // read is 16*63 + 16*MT - 1 + (Lmax - L) <= kBT + Lmax + 14.
-  constexpr int WX = kBT + PRUNE_MAX_L + 16;
-  __shared__ float2 s_g[kBT];
-  __shared__ float4 s_x[WX];
-  __shared__ float2 s_w[kNW][16][17];
-  // Slab partials of each tap: tap l collects diagonals of at most two
-  // adjacent slabs (mt with 16 mt in [L-1-l-15, L-1-l+15]), which differ in
-  // parity, so they are kept by slab parity and added in parity order.
+                                                    float2 *__restrict__ partial, uint32_t run) {
+  __shared__ float4 s_g[kBT];
+  // basis planes; after a run's tiles the same memory is the waves' W scratch
+  __shared__ float2 s_u[kGH][kWX];
   __shared__ float2 s_pd[kMKH][2][PRUNE_MAX_L];
+  float2 (*s_w)[16][17] = reinterpret_cast<float2 (*)[16][17]>(&s_u[0][0]);
+  static_assert(kNW * 16 * 17 <= kGH * kWX, "W scratch fits in the basis planes");
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int li = lane & 15, lk = lane >> 4;
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const uint32_t D = d.n_banks * d.Kmax;
   const uint32_t ni = *n_items;
-  for (uint32_t it = blockIdx.x; it < ni; it += gridDim.x) {
-    const WorkItem wi = items[it];
-    const BwdFrame F = bf[wi.frame];
-    const int n = (int)F.n, n0 = (int)wi.tile * kBT;
-    float2 *prow = partial + (size_t)it * D * Lmax;
-    if (F.route) {
-      for (uint32_t k = t; k < D * Lmax; k += kWG) prow[k] = make_float2(0.f, 0.f);
-      continue;
-    }
-    for (int k = t; k < kBT; k += kWG) s_g[k] = n0 + k < n ? F.g[n0 + k] : make_float2(0.f, 0.f);
-    for (int k = t; k < WX; k += kWG) {
-      const int p = n0 - ((int)Lmax - 1) + k;
-      float2 v = make_float2(0.f, 0.f);
-      if (p < n && p >= -(int)F.t0) v = F.x[p];
-      s_x[k] = make_float4(v.x, v.y, sqrtf(v.x * v.x + v.y * v.y), 0.f);
-    }
-    const uint32_t kfull = (1u << d.Kmax) - 1u;
-    for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
-      const uint32_t bmask = (F.mask >> (bank * d.Kmax)) & kfull;
-      float2 *brow = prow + (size_t)bank * d.Kmax * Lmax;
-      if (!bmask) {
-        for (uint32_t k = t; k < d.Kmax * Lmax; k += kWG) brow[k] = make_float2(0.f, 0.f);
+  const uint32_t R = min(max(run, 1u), (uint32_t)kMaxRun);
+  const uint32_t ng = (ni + R - 1) / R;
+  const uint32_t kfull = (1u << d.Kmax) - 1u;
+  for (uint32_t grp = blockIdx.x; grp < ng; grp += gridDim.x) {
+    const uint32_t i1 = min(ni, (grp + 1) * R);
+    for (uint32_t r0 = grp * R; r0 < i1;) {
+      const WorkItem w0 = items[r0];
+      uint32_t r1 = r0 + 1;
+      while (r1 < i1 && items[r1].frame == w0.frame) ++r1;
+      const BwdFrame F = bf[w0.frame];
+      const int n = (int)F.n;
+      // rows of the run's later items are zero
+      for (uint32_t k = t; k < (r1 - r0 - 1) * D * Lmax; k += kWG)
+        partial[(size_t)(r0 + 1) * D * Lmax + k] = make_float2(0.f, 0.f);
+      float2 *prow = partial + (size_t)r0 * D * Lmax;
+      if (F.route) {
+        for (uint32_t k = t; k < D * Lmax; k += kWG) prow[k] = make_float2(0.f, 0.f);
+        r0 = r1;
         continue;
       }
-      const int KH = 32 - __clz(bmask);
-      const int L = (int)d.L[bank];
-      const int MT = (L + 15 + 15) / 16;
-      for (int k = t; k < kMKH * 2 * PRUNE_MAX_L; k += kWG) (&s_pd[0][0][0])[k] = make_float2(0.f, 0.f);
-      __syncthreads();   // windows written, s_pd cleared
-      // units: (slab mt, branches 2q and 2q+1)
-      const int NQ = (KH + 1) / 2;
-      const int units = NQ * MT;
-      for (int u = w; u < units; u += kNW) {
-        const int q = u / MT, mt = u - q * MT;
-        const int b0 = 2 * q, nb = min(2, KH - b0);
-        const uint32_t um = (bmask >> b0) & ((1u << nb) - 1u);
-        if (!um) continue;
-        floatx4 acc[2][3];
+      for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+        const uint32_t bmask = (F.mask >> (bank * d.Kmax)) & kfull;
+        float2 *brow = prow + (size_t)bank * d.Kmax * Lmax;
+        if (!bmask) {
+          for (uint32_t k = t; k < d.Kmax * Lmax; k += kWG) brow[k] = make_float2(0.f, 0.f);
+          continue;
+        }
+        const int KH = 32 - __clz(bmask);
+        const int L = (int)d.L[bank];
+        const int MT = (L + 15 + 15) / 16;
+        __syncthreads();   // earlier readers of s_pd are done
+        for (int k = t; k < kMKH * 2 * PRUNE_MAX_L; k += kWG) (&s_pd[0][0][0])[k] = make_float2(0.f, 0.f);
+        for (int b0 = 0; b0 < KH; b0 += kGH) {
+          const int nb = min(kGH, KH - b0);
+          const int units = MT * nb;   // unit u: slab u / nb, branch b0 + u % nb
+          floatx4 acc[kUMax][3];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[j][0] = acc[j][1] = acc[j][2] = floatx4{0.f, 0.f, 0.f, 0.f};
-        // A(row li, block 4s+lk) = g[16(4s+lk) + li];
-        // B(block 4s+lk, column li of slab mt) = conj u_b at x-window index
-        //   16(4s+lk) + 16 mt + li + (Lmax - L)
-        const int xb = 16 * lk + 16 * mt + li + ((int)Lmax - L);
-        const int gb = 16 * lk + li;
-        if (nb == 2) gh_unit<2>(s_g, s_x, gb, xb, b0, acc);
-        else gh_unit<1>(s_g, s_x, gb, xb, b0, acc);
-        for (int j = 0; j < nb; ++j) {
-          const int b = b0 + j;
-          if (!((bmask >> b) & 1u)) continue;
-          // W tile (rows 4lk+e, column li) to the wave's scratch
+          for (int k = 0; k < kUMax; ++k) acc[k][0] = acc[k][1] = acc[k][2] = floatx4{0.f, 0.f, 0.f, 0.f};
+          for (uint32_t it = r0; it < r1; ++it) {
+            const int n0 = (int)items[it].tile * kBT;
+            __syncthreads();   // earlier readers of s_g / s_u are done
+            {
+              // all of this thread's loads first, then the stores
+              constexpr int NG = kBT / kWG, NX = (kWX + kWG - 1) / kWG;
+              float2 gv[NG], xv[NX];
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            s_w[w][4 * lk + e][li] =
-                make_float2(acc[j][0][e] - acc[j][1][e], acc[j][2][e] - acc[j][0][e] - acc[j][1][e]);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // lane 0..30: diagonal j - i = lane - 15, tap l = L-1 - 16 mt - (j - i)
-          if (lane < 31) {
-            const int dl = lane - 15;
-            const int l = L - 1 - 16 * mt - dl;
-            if (l >= 0 && l < L) {
-              float sr = 0.f, si = 0.f;
-              for (int i = max(0, -dl); i < min(16, 16 - dl); ++i) {
-                const float2 v = s_w[w][i][i + dl];
-                sr += v.x;
-                si += v.y;
+              for (int i = 0; i < NG; ++i) {
+                const int k = t + i * kWG;
+                gv[i] = n0 + k < n ? F.g[n0 + k] : make_float2(0.f, 0.f);
               }
-              s_pd[b][mt & 1][l] = make_float2(sr, si);
+              // u-plane index k holds position n0 - (Lmax-1) + k
+#pragma unroll
+              for (int i = 0; i < NX; ++i) {
+                const int k = t + i * kWG, p = n0 - ((int)Lmax - 1) + k;
+                xv[i] = (k < kWX && p < n && p >= -(int)F.t0) ? F.x[p] : make_float2(0.f, 0.f);
+              }
+#pragma unroll
+              for (int i = 0; i < NG; ++i)
+                s_g[t + i * kWG] = make_float4(gv[i].x, gv[i].y, gv[i].x + gv[i].y, 0.f);
+#pragma unroll
+              for (int i = 0; i < NX; ++i) {
+                const int k = t + i * kWG;
+                if (k < kWX) {
+                  const float r = sqrtf(xv[i].x * xv[i].x + xv[i].y * xv[i].y);
+                  float rp = ipow(r, b0);
+#pragma unroll
+                  for (int j = 0; j < kGH; ++j) {
+                    if (j < nb) s_u[j][k] = make_float2(xv[i].x * rp, -(xv[i].y * rp));
+                    rp *= r;
+                  }
+                }
+              }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kUMax; ++k) {
+              const int u = w + kNW * k;
+              if (u < units) {
+                const int mt = u / nb, j = u - mt * nb;
+                if ((bmask >> (b0 + j)) & 1u)
+                  gh_tile(s_g, s_u[j], 16 * lk + li, 16 * lk + 16 * mt + li + ((int)Lmax - L), acc[k]);
+              }
             }
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          __syncthreads();   // the basis planes become the W scratch
+#pragma unroll
+          for (int k = 0; k < kUMax; ++k) {
+            const int u = w + kNW * k;
+            if (u >= units) continue;
+            const int mt = u / nb, j = u - mt * nb, b = b0 + j;
+            if (!((bmask >> b) & 1u)) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              s_w[w][4 * lk + e][li] =
+                  make_float2(acc[k][0][e] - acc[k][1][e], acc[k][2][e] - acc[k][0][e] - acc[k][1][e]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // lane 0..30: diagonal j - i = lane - 15, tap l = L-1 - 16 mt - (j - i),
+            // 16 predicated reads in a fixed order
+            if (lane < 31) {
+              const int dl = lane - 15;
+              const int l = L - 1 - 16 * mt - dl;
+              if (l >= 0 && l < L) {
+                float2 v[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                  const int jj = i + dl;
+                  v[i] = s_w[w][i][min(15, max(0, jj))];
+                  if (jj < 0 || jj > 15) v[i] = make_float2(0.f, 0.f);
+                }
+                float sr = 0.f, si = 0.f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                  sr += v[i].x;
+                  si += v[i].y;
+                }
+                s_pd[b][mt & 1][l] = make_float2(sr, si);
+              }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
+        }
+        __syncthreads();
+        for (uint32_t k = t; k < d.Kmax * Lmax; k += kWG) {
+          const int b = (int)(k / Lmax), l = (int)(k - b * Lmax);
+          float2 v = make_float2(0.f, 0.f);
+          if (b < KH && ((bmask >> b) & 1u) && l < L) {
+            v.x = s_pd[b][0][l].x + s_pd[b][1][l].x;
+            v.y = s_pd[b][0][l].y + s_pd[b][1][l].y;
+          }
+          brow[k] = v;
         }
       }
-      __syncthreads();
-      for (uint32_t k = t; k < d.Kmax * Lmax; k += kWG) {
-        const int b = (int)(k / Lmax), l = (int)(k - b * Lmax);
-        float2 v = make_float2(0.f, 0.f);
-        if (b < KH && ((bmask >> b) & 1u) && l < L) {
-          v.x = s_pd[b][0][l].x + s_pd[b][1][l].x;
-          v.y = s_pd[b][0][l].y + s_pd[b][1][l].y;
-        }
-        brow[k] = v;
-      }
-      __syncthreads();   // s_pd is cleared for the next bank
+      __syncthreads();   // LDS is rewritten by the next run
+      r0 = r1;
     }
-    __syncthreads();     // windows are rewritten by the next item
   }
 }
 
@@ -337,8 +411,11 @@ void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkIt
 }
 
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
-                        const uint32_t *n_items, float2 *partial, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_gh_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, partial);
+                        const uint32_t *n_items, float2 *partial, uint32_t max_items,
+                        uint32_t grid, hipStream_t s) {
+  // tiles per run: as many as keep every workgroup of the grid busy
+  const uint32_t run = std::max<uint32_t>(1, std::min<uint32_t>(kMaxRun, max_items / std::max(1u, grid)));
+  hipLaunchKernelGGL(k_bwd_gh_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, partial, run);
 }
 
 }  // namespace prune

@@ -139,15 +139,28 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
       const int L = (int)d.L[bank];
       const int Lpad = (L + J - 1) / J * J;
       __syncthreads();
-      for (int k = t; k < T + Lpad - 1; k += WG) {
-        const int p = n0 - (Lpad - 1) + k;
-        float2 v = make_float2(0.f, 0.f);
-        if (p >= 0) {
-          if (p < n) v = d.x[p];
-        } else if (-p <= (int)d.halo_valid) {
-          v = d.halo[Hd + p];
+      {
+        // all of this thread's loads first, then the stores (one memory latency)
+        constexpr int NIT = (T + PRUNE_MAX_L - 1 + WG - 1) / WG;
+        const int WN = T + Lpad - 1;
+        float2 v[NIT];
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+          const int k = t + i * WG, p = n0 - (Lpad - 1) + k;
+          v[i] = make_float2(0.f, 0.f);
+          if (k < WN) {
+            if (p >= 0) {
+              if (p < n) v[i] = d.x[p];
+            } else if (-p <= (int)d.halo_valid) {
+              v[i] = d.halo[Hd + p];
+            }
+          }
         }
-        win[pidx(k)] = make_float4(v.x, v.y, sqrtf(v.x * v.x + v.y * v.y), 0.f);
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+          const int k = t + i * WG;
+          if (k < WN) win[pidx(k)] = make_float4(v[i].x, v[i].y, sqrtf(v[i].x * v[i].x + v[i].y * v[i].y), 0.f);
+        }
       }
       const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
       for (int k = t; k < KH * Lpad; k += WG) {

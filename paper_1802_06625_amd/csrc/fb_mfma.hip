@@ -19,9 +19,9 @@
 // of block li: four consecutive samples.
 //
 // A tile is NW waves x NT result tiles x 256 outputs.  LDS holds the tile's
-// input window as three fp32 planes (re, im, r = |x|) with 4 pad floats per
-// 16 (the 16 lanes of a B fragment read 16 samples apart; the pad spreads
-// them over distinct banks), and each active branch's taps as
+// input window as three fp32 planes (re, im, r = |x|) with one pad float per
+// 16 (the 16 lanes of a B fragment read 16 samples apart; an odd stride of
+// 17 puts them in distinct banks), and each active branch's taps as
 // {hr, hi, hr + hi, 0} with zeros on both sides, so every Toeplitz element is
 // one table read.  u_b is formed in registers from the window by repeated
 // multiplication with r.  Workgroups take tiles from the item list with an
@@ -38,7 +38,7 @@ constexpr int kHOff = 20;                  // table index of tap l = 0
 constexpr int kHQ = PRUNE_MAX_L + 36;      // table entries per branch: l = -20 .. L+15
 constexpr int kMKH = 10;                   // branches per bank
 
-__device__ __forceinline__ int widx(int k) { return k + 4 * (k >> 4); }
+__device__ __forceinline__ int widx(int k) { return k + (k >> 4); }
 
 // One bank: S steps of 4 along m for the NT result tiles of this wave.
 //  kb: window index of B element (m = 0, tile 0) for this lane;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
   // Window positions: the last B element read is at T + Lmax + 1 (m runs to
   // 4 ceil((L+15)/4) - 1 <= L + 17), so T + PRUNE_MAX_L + 2 covers it.
   constexpr int WN = T + PRUNE_MAX_L + 2;
-  constexpr int WS = WN + 4 * (WN >> 4) + 4;
+  constexpr int WS = WN + (WN >> 4) + 1;
   __shared__ float s_wr[WS], s_wi[WS], s_wm[WS];
   __shared__ float4 s_h[kMKH * kHQ];
   __shared__ uint32_t s_item;
@@ -147,18 +147,32 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
 
     // Window index k holds stream position n0 - (Lw-1) + k.
     const int Lw = (int)d.Lmax;
-    for (int k = t; k < WN; k += WG) {
-      const int p = n0 - (Lw - 1) + k;
-      float2 v = make_float2(0.f, 0.f);
-      if (p >= 0) {
-        if (p < n) v = d.x[p];
-      } else if (-p <= (int)d.halo_valid) {
-        v = d.halo[Lw - 1 + p];
+    {
+      // all of this thread's loads first, then the stores (one memory latency)
+      constexpr int NIT = (WN + WG - 1) / WG;
+      float2 v[NIT];
+#pragma unroll
+      for (int i = 0; i < NIT; ++i) {
+        const int k = t + i * WG, p = n0 - (Lw - 1) + k;
+        v[i] = make_float2(0.f, 0.f);
+        if (k < WN) {
+          if (p >= 0) {
+            if (p < n) v[i] = d.x[p];
+          } else if (-p <= (int)d.halo_valid) {
+            v[i] = d.halo[Lw - 1 + p];
+          }
+        }
       }
-      const int q = widx(k);
-      s_wr[q] = v.x;
-      s_wi[q] = v.y;
-      s_wm[q] = sqrtf(v.x * v.x + v.y * v.y);
+#pragma unroll
+      for (int i = 0; i < NIT; ++i) {
+        const int k = t + i * WG;
+        if (k < WN) {
+          const int q = widx(k);
+          s_wr[q] = v[i].x;
+          s_wi[q] = v[i].y;
+          s_wm[q] = sqrtf(v[i].x * v[i].x + v[i].y * v[i].y);
+        }
+      }
     }
 
     floatx4 a1[NT], a2[NT], a3[NT];
