@@ -335,6 +335,8 @@ typedef struct {
 /* y = filter bank of x (the forward of the merged DPG over whole streams,
  * including passthrough-routed frames).  x, y: device [S][N] complex64;
  * taps: device [S][n_banks][Kmax][Lmax] complex64; frames: device array.
+ * The frames of one stream are consecutive in the array, in increasing t0,
+ * and do not overlap; samples of y outside every frame are not written.
  * E_UNSUPPORTED beyond the limits, E_ARG on inconsistent descriptors. */
 prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const void *taps,
                               const void *frames, void *y, prune_stream_t stream);

@@ -21,10 +21,14 @@ struct BwdFrame {
 // one frame each) as the vector kernel:
 //  grad_x at the tile's inputs from the frame's own outputs, and
 //  the tile's grad_h partial, row (bank * Kmax + b) * Lmax + l of partial[item].
+// Workgroups take work with an atomic ticket (*ticket zero at launch).
+// The grad_x kernel also computes each frame's halo gradient into hg
+// ([n_frames][Lmax-1], as the vector halo kernel does).
 void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
-                        const uint32_t *n_items, uint32_t grid, hipStream_t s);
+                        const uint32_t *n_items, unsigned int *ticket, float2 *hg, uint32_t grid,
+                        hipStream_t s);
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
-                        const uint32_t *n_items, float2 *partial, uint32_t max_items,
-                        uint32_t grid, hipStream_t s);
+                        const uint32_t *n_items, unsigned int *ticket, float2 *partial,
+                        uint32_t max_items, uint32_t grid, hipStream_t s);
 
 }  // namespace prune

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(1024) void k_direct_prep(prune_fb_desc d, const flo
                                                       unsigned int *ticket, uint32_t *err) {
   __shared__ uint32_t sm[32];
   __shared__ uint32_t s_carry;
+  __shared__ uint32_t s_pre[1024], s_tl[1024];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
   uint32_t Lmax = 1;
@@ -78,11 +79,18 @@ __global__ __launch_bounds__(1024) void k_direct_prep(prune_fb_desc d, const flo
     }
     __syncthreads();
     const uint32_t pre = s_carry + (wid ? sm[wid - 1] : 0u) + v - tiles;
-    for (uint32_t k = 0; k < tiles; ++k) {
-      WorkItem it;
-      it.frame = f;
-      it.tile = k;
-      items[pre + k] = it;
+    s_pre[tid] = pre;
+    s_tl[tid] = tiles;
+    __syncthreads();
+    // tiles of frame base+j written by wave j mod nw, lanes on consecutive items
+    for (uint32_t j = wid; j < (uint32_t)nt && base + j < d.n_frames; j += nw) {
+      const uint32_t p0 = s_pre[j], nj = s_tl[j];
+      for (uint32_t k = lane; k < nj; k += 64) {
+        WorkItem it;
+        it.frame = base + j;
+        it.tile = k;
+        items[p0 + k] = it;
+      }
     }
     __syncthreads();
     if (tid == 0) s_carry += sm[nw - 1];

@@ -50,14 +50,16 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
                                                    const float2 *taps, const prune_fb_frame *fr,
                                                    const float2 *g, float2 *gx, BwdFrame *bf,
                                                    WorkItem *items, uint32_t *n_items,
-                                                   uint32_t *s_begin, uint32_t *s_end) {
+                                                   uint32_t *s_begin, uint32_t *s_end,
+                                                   unsigned long long *cov) {
   __shared__ uint32_t sm[32];
   __shared__ uint32_t s_carry;
+  __shared__ uint32_t s_pre[1024], s_tl[1024];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const size_t tstride = (size_t)d.n_banks * d.Kmax * Lmax;
-  for (uint32_t s = tid; s < d.n_streams; s += nt) { s_begin[s] = 0; s_end[s] = 0; }
+  for (uint32_t s = tid; s < d.n_streams; s += nt) { s_begin[s] = 0; s_end[s] = 0; cov[s] = 0ull; }
   if (tid == 0) s_carry = 0;
   __syncthreads();
   for (uint32_t base = 0; base < d.n_frames; base += nt) {
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
       b.pad0 = b.pad1 = b.pad2 = 0;
       bf[f] = b;
       tiles = (b.n + kBT - 1) / kBT;
+      if (b.n) atomicAdd(&cov[q.stream], (unsigned long long)b.n);   // samples covered
     }
     uint32_t v = tiles;
     for (int o = 1; o < 64; o <<= 1) {
@@ -94,13 +97,20 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
     }
     __syncthreads();
     const uint32_t pre = s_carry + (wid ? sm[wid - 1] : 0u) + v - tiles;
-    if (f < d.n_frames) {
-      for (uint32_t k = 0; k < tiles; ++k) {
+    s_pre[tid] = pre;
+    s_tl[tid] = tiles;
+    __syncthreads();
+    // tiles of frame base+j written by wave j mod nw, lanes on consecutive items
+    for (uint32_t j = wid; j < (uint32_t)nt && base + j < d.n_frames; j += nw) {
+      const uint32_t p0 = s_pre[j], nj = s_tl[j];
+      for (uint32_t k = lane; k < nj; k += 64) {
         WorkItem it;
-        it.frame = f;
+        it.frame = base + j;
         it.tile = k;
-        items[pre + k] = it;
+        items[p0 + k] = it;
       }
+    }
+    if (f < d.n_frames) {
       if (q.stream < d.n_streams) {
         if (f == 0 || fr[f - 1].stream != q.stream) s_begin[q.stream] = pre;
         if (f + 1 == d.n_frames || fr[f + 1].stream != q.stream) s_end[q.stream] = pre + tiles;
@@ -110,7 +120,23 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
     if (tid == 0) s_carry += sm[nw - 1];
     __syncthreads();
   }
-  if (tid == 0) *n_items = s_carry;
+  if (tid == 0) {
+    n_items[0] = s_carry;
+    n_items[1] = 0u;   // work tickets of the matrix-core adjoint kernels
+    n_items[2] = 0u;
+  }
+}
+
+// Zero grad_x of streams whose frames do not cover every sample (the
+// kernels write grad_x only inside frames).  Workgroup (stream, chunk).
+__global__ __launch_bounds__(256) void k_bwd_gapfill(prune_fb_desc d, const unsigned long long *cov,
+                                                     float2 *gx) {
+  const uint32_t s = blockIdx.x;
+  if (cov[s] == (unsigned long long)d.stream_len) return;
+  const uint64_t per = (d.stream_len + gridDim.y - 1) / gridDim.y;
+  const uint64_t lo = (uint64_t)blockIdx.y * per, hi = min(lo + per, (uint64_t)d.stream_len);
+  float2 *row = gx + (size_t)s * d.stream_len;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) row[i] = make_float2(0.f, 0.f);
 }
 
 // grad_x of the J inputs a lane owns for one chunk of J taps.
@@ -379,35 +405,37 @@ __global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame
   hg[(size_t)f * H + k] = out;
 }
 
-// Add later frames' halo gradients into grad_x (frames of a stream are
-// consecutive and in order).  Thread per (frame, one of its last H samples).
+// Add the halo gradients into grad_x.  Stream sample q before a frame start
+// (q in [t0 - H, t0)) is owned by the first frame of its stream that starts
+// after q; that frame's thread (frame, q - (t0 - H)) adds, in frame order,
+// the halo gradients of every frame whose window covers q.  Samples inside an
+// earlier frame already hold that frame's own contribution; samples in a gap
+// between frames hold zero.  Each sample is written by one thread, no atomics.
 __global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_frame *__restrict__ fr,
                                                 const BwdFrame *__restrict__ bf,
-                                                const float2 *__restrict__ hg) {
+                                                const float2 *__restrict__ hg, float2 *__restrict__ gx) {
   const uint32_t f = blockIdx.x;
   if (f >= d.n_frames) return;
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const int H = (int)Lmax - 1;
-  const BwdFrame F = bf[f];
   const int k = threadIdx.x;
-  if (k >= H || !F.n) return;
-  const int local = (int)F.n - H + k;      // sample of this frame
-  if (local < 0) return;
-  const uint64_t q = (uint64_t)F.t0 + local;
-  float2 acc = F.gx[local];
-  for (uint32_t f2 = f + 1; f2 < d.n_frames; ++f2) {
-    const prune_fb_frame G = fr[f2];
-    if (G.stream != F.stream || (uint64_t)G.t0 > q + H) break;
-    if (G.route || !bf[f2].n) continue;
-    const int64_t pos = (int64_t)q - ((int64_t)G.t0 - H);   // index in G's halo
-    if (pos >= 0 && pos < H) {
-      const float2 v = hg[(size_t)f2 * H + pos];
-      acc.x += v.x;
-      acc.y += v.y;
-    }
+  const prune_fb_frame G = fr[f];
+  if (k >= H || G.stream >= d.n_streams) return;
+  const int64_t q = (int64_t)G.t0 - H + k;
+  if (q < 0) return;
+  if (f > 0 && fr[f - 1].stream == G.stream && q < (int64_t)fr[f - 1].t0) return;   // not the owner
+  float2 acc = make_float2(0.f, 0.f);
+  for (uint32_t f2 = f; f2 < d.n_frames; ++f2) {
+    const prune_fb_frame G2 = fr[f2];
+    if (G2.stream != G.stream || (int64_t)G2.t0 - H > q) break;
+    if (G2.route || !bf[f2].n) continue;
+    const float2 v = hg[(size_t)f2 * H + (size_t)(q - ((int64_t)G2.t0 - H))];
+    acc.x += v.x;
+    acc.y += v.y;
   }
-  F.gx[local] = acc;
+  float2 &out = gx[(size_t)G.stream * d.stream_len + (size_t)q];
+  out = make_float2(out.x + acc.x, out.y + acc.y);
 }
 
 // Two-stage fixed-order float64 reduction of the tile partials of each
@@ -481,7 +509,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const doub
 }
 
 struct BwdLayout {
-  size_t frames, items, partial, part2, hg, sbeg, send, cnt, total;
+  size_t frames, items, partial, part2, hg, sbeg, send, cov, cnt, total;
   uint32_t max_items, E, H;
 };
 
@@ -502,6 +530,7 @@ static BwdLayout bwd_layout(const prune_fb_desc &d) {
   L.hg = o; o = al(o + (size_t)d.n_frames * std::max<uint32_t>(L.H, 1) * sizeof(float2));
   L.sbeg = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
   L.send = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
+  L.cov = o; o = al(o + (size_t)d.n_streams * sizeof(unsigned long long));
   L.cnt = o; o = al(o + 16);
   L.total = o;
   return L;
@@ -593,32 +622,39 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   float2 *hg = (float2 *)(w + L.hg);
   uint32_t *sb = (uint32_t *)(w + L.sbeg), *se = (uint32_t *)(w + L.send);
   uint32_t *cnt = (uint32_t *)(w + L.cnt);
+  unsigned long long *cov = (unsigned long long *)(w + L.cov);
   const prune_fb_desc d = *desc;
-  // grad_x starts as zero outside the frames' coverage
-  if (hipMemsetAsync(gx, 0, (size_t)d.n_streams * d.stream_len * sizeof(float2), s) != hipSuccess)
-    return PRUNE_E_HIP;
   if (d.n_frames == 0) {
+    if (hipMemsetAsync(gx, 0, (size_t)d.n_streams * d.stream_len * sizeof(float2), s) != hipSuccess)
+      return PRUNE_E_HIP;
     if (hipMemsetAsync(gtaps, 0, (size_t)d.n_streams * L.E * sizeof(float2), s) != hipSuccess)
       return PRUNE_E_HIP;
     return PRUNE_OK;
   }
   hipLaunchKernelGGL(k_bwd_prep, dim3(1), dim3(1024), 0, s, d, (const float2 *)x, (const float2 *)taps,
                      (const prune_fb_frame *)frames, (const float2 *)gy, (float2 *)gx, bf, items, cnt,
-                     sb, se);
+                     sb, se, cov);
+  // grad_x starts as zero outside the frames' coverage
+  hipLaunchKernelGGL(k_bwd_gapfill, dim3(d.n_streams, 64), dim3(256), 0, s, d, cov, (float2 *)gx);
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
   if (variant == 2) {
-    launch_bwd_gu_mfma(d, bf, items, cnt, grid, s);
-    launch_bwd_gh_mfma(d, bf, items, cnt, partial, L.max_items, grid, s);
+    // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids at
+    // the kernels' occupancy (3 and 2 workgroups per CU)
+    launch_bwd_gu_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg,
+                       std::min<uint32_t>(L.max_items + d.n_frames, (uint32_t)ncu * 3), s);
+    launch_bwd_gh_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 2), partial, L.max_items,
+                       (uint32_t)ncu * 2, s);
   } else {
     hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
   }
   if (L.H) {
-    hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
+    if (variant != 2)   // the matrix-core grad_x kernel computes the halo rows itself
+      hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
     hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
-                       bf, hg);
+                       bf, hg, (float2 *)gx);
   }
   const uint32_t eblocks = (L.E + 63) / 64;
   hipLaunchKernelGGL(k_bwd_reduce1, dim3(d.n_streams, eblocks, kRedG), dim3(256), 0, s, d, partial, sb,

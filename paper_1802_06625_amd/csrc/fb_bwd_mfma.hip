@@ -86,9 +86,15 @@ __device__ __forceinline__ void gu_group(const float2 *__restrict__ gw, const fl
 }  // namespace
 
 // ------------------------------------------------------------------ grad_x
+// Tickets 0 .. n_items-1 are the tiles; tickets n_items .. n_items+n_frames-1
+// are halo items: the gradient of the H = Lmax-1 stream samples before frame
+// f from f's own outputs (positions -64 .. -1 of a tile at -64, computed by
+// wave 0), written to hg[f][0 .. H) for the fix-up kernel.
 __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdFrame *__restrict__ bf,
                                                     const WorkItem *__restrict__ items,
-                                                    const uint32_t *__restrict__ n_items) {
+                                                    const uint32_t *__restrict__ n_items,
+                                                    unsigned int *__restrict__ ticket,
+                                                    float2 *__restrict__ hg) {
   // G window: index k holds g at tile position k; the last one read is
   // 256*3 + 16*15 + 3 + 4*(S-1) <= kBT + L + 1.
   constexpr int WN = kBT + PRUNE_MAX_L + 2;
@@ -99,16 +105,27 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
   const int li = lane & 15, lk = lane >> 4;
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  __shared__ uint32_t s_item;
   const uint32_t ni = *n_items;
-  for (uint32_t it = blockIdx.x; it < ni; it += gridDim.x) {
-    const WorkItem wi = items[it];
-    const BwdFrame F = bf[wi.frame];
-    const int n = (int)F.n, n0 = (int)wi.tile * kBT;
+  const int H = (int)Lmax - 1;
+  const uint32_t nh = H > 0 ? d.n_frames : 0u;
+  for (;;) {
+    if (t == 0) s_item = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    __syncthreads();   // s_item is rewritten by the next ticket
+    if (it >= ni + nh) break;
+    const bool halo = it >= ni;
+    const uint32_t frame = halo ? it - ni : items[it].frame;
+    const BwdFrame F = bf[frame];
+    const int n = (int)F.n, n0 = halo ? -64 : (int)items[it].tile * kBT;
+    if (halo && (F.route || n == 0)) continue;   // the fix-up skips these frames
     if (F.route) {
       for (int k = t; k < kBT; k += kWG)
         if (n0 + k < n) F.gx[n0 + k] = F.g[n0 + k];
       continue;
     }
+    const bool work = !halo || w == 0;   // a halo item needs wave 0's block only
     {
       // all of this thread's loads first, then the stores (one memory latency)
       constexpr int NIT = (WN + kWG - 1) / kWG;
@@ -116,7 +133,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
 #pragma unroll
       for (int i = 0; i < NIT; ++i) {
         const int k = t + i * kWG, q = n0 + k;   // outputs of this frame only
-        v[i] = (k < WN && q < n) ? F.g[q] : make_float2(0.f, 0.f);
+        v[i] = (k < WN && q >= 0 && q < n) ? F.g[q] : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int i = 0; i < NIT; ++i) {
@@ -129,7 +146,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
     float xr[4], xi[4], rr[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float2 v = m0 + e < n ? F.x[m0 + e] : make_float2(0.f, 0.f);
+      const int m = m0 + e;   // stream history before the frame: m >= -t0
+      const float2 v = (m < n && m >= -(int)F.t0) ? F.x[m] : make_float2(0.f, 0.f);
       xr[e] = v.x;
       xi[e] = v.y;
       rr[e] = sqrtf(v.x * v.x + v.y * v.y);
@@ -166,7 +184,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
       const int kb = 256 * w + 16 * li + lk;
       const float4 *hb = s_h + (lk - li + kHOff);
       float rp[4] = {1.f, 1.f, 1.f, 1.f};   // r^b of the group's next branch
-      for (int b0 = 0; b0 < KH; b0 += kGB) {
+      for (int b0 = 0; work && b0 < KH; b0 += kGB) {
         floatx4 acc[kGB][3];
 #pragma unroll
         for (int j = 0; j < kGB; ++j) acc[j][0] = acc[j][1] = acc[j][2] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -202,7 +220,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int m = m0 + e;
-      if (m < n) {
+      if (halo ? (w == 0 && m >= -H && m < 0) : m < n) {
         float gr = s1r[e], gi = s1i[e];
         const float r2 = xr[e] * xr[e] + xi[e] * xi[e];
         if (r2 > 0.f) {
@@ -210,7 +228,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
           gr += er * s2r[e] - ei * s2i[e];
           gi += er * s2i[e] + ei * s2r[e];
         }
-        F.gx[m] = make_float2(gr, gi);
+        if (halo) hg[(size_t)frame * H + (m + H)] = make_float2(gr, gi);
+        else F.gx[m] = make_float2(gr, gi);
       }
     }
     __syncthreads();   // s_g and s_h are rewritten by the next item
@@ -250,6 +269,7 @@ __device__ __forceinline__ void gh_tile(const float4 *__restrict__ gp, const flo
 __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdFrame *__restrict__ bf,
                                                     const WorkItem *__restrict__ items,
                                                     const uint32_t *__restrict__ n_items,
+                                                    unsigned int *__restrict__ ticket,
                                                     float2 *__restrict__ partial, uint32_t run) {
   __shared__ float4 s_g[kBT];
   // basis planes; after a run's tiles the same memory is the waves' W scratch
@@ -266,7 +286,13 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
   const uint32_t R = min(max(run, 1u), (uint32_t)kMaxRun);
   const uint32_t ng = (ni + R - 1) / R;
   const uint32_t kfull = (1u << d.Kmax) - 1u;
-  for (uint32_t grp = blockIdx.x; grp < ng; grp += gridDim.x) {
+  __shared__ uint32_t s_grp;
+  for (;;) {
+    if (t == 0) s_grp = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t grp = s_grp;
+    __syncthreads();   // s_grp is rewritten by the next ticket
+    if (grp >= ng) break;
     const uint32_t i1 = min(ni, (grp + 1) * R);
     for (uint32_t r0 = grp * R; r0 < i1;) {
       const WorkItem w0 = items[r0];
@@ -406,16 +432,19 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
 }
 
 void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
-                        const uint32_t *n_items, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_gu_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items);
+                        const uint32_t *n_items, unsigned int *ticket, float2 *hg, uint32_t grid,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd_gu_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, ticket, hg);
 }
 
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
-                        const uint32_t *n_items, float2 *partial, uint32_t max_items,
-                        uint32_t grid, hipStream_t s) {
-  // tiles per run: as many as keep every workgroup of the grid busy
-  const uint32_t run = std::max<uint32_t>(1, std::min<uint32_t>(kMaxRun, max_items / std::max(1u, grid)));
-  hipLaunchKernelGGL(k_bwd_gh_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, partial, run);
+                        const uint32_t *n_items, unsigned int *ticket, float2 *partial,
+                        uint32_t max_items, uint32_t grid, hipStream_t s) {
+  // tiles per run: up to kMaxRun, about one run per workgroup of the grid
+  const uint32_t run =
+      std::max<uint32_t>(1, std::min<uint32_t>(kMaxRun, max_items / std::max(1u, grid)));
+  hipLaunchKernelGGL(k_bwd_gh_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, ticket,
+                     partial, run);
 }
 
 }  // namespace prune

@@ -154,3 +154,33 @@ def test_fit_tracks_oracle_adam():
     losses = np.array(losses)
     np.testing.assert_allclose(losses, ref_losses[:steps], rtol=1e-3)
     assert losses[-1] < 0.5 * losses[0]
+
+
+@pytest.mark.parametrize("form", BWD_FORMS)
+def test_backward_frames_with_gaps(form):
+    """Frames that leave gaps: before the first frame, between frames (shorter
+    and longer than the filter history) and after the last one.  Gap samples
+    that a later frame's window reads get that frame's halo gradient; the
+    others are zero."""
+    announce(f"backward gaps form {form}")
+    wl = synth.make("C5", n_frames=6, frame_len=3000, n_streams=2, cotangent=True)
+    L = wl.bank_L[0]
+    layout = [(40, 2000), (2050, 1500), (3600, 5), (3700, 900), (4640, 3000), (9000, 2000)]
+    rows = []
+    for s_ in range(2):
+        for i, (t0, n) in enumerate(layout):
+            rows.append((s_, t0 + 7 * s_, n, 0x7F, int(i == 2 and s_ == 1)))
+    fr = ops.frame_table(rows)
+    mfl = max(n for _, _, n, _, _ in rows)
+    gx, gt = _backward(torch.from_numpy(wl.x).cuda(), torch.from_numpy(wl.taps).cuda(), fr,
+                       torch.from_numpy(wl.gy).cuda(), wl.Kmax, wl.bank_L, mfl, form)
+    for s_ in range(2):
+        ref = [(t0, n, m, r) for (ss, t0, n, m, r) in rows if ss == s_]
+        rx, rt = fb_stream_adjoint(wl.x[s_], ref, wl.taps[s_], wl.bank_L, wl.Kmax, wl.gy[s_])
+        assert rel_l2(gx[s_], rx) <= TOL, (s_, rel_l2(gx[s_], rx))
+        assert rel_l2(gt[s_], rt) <= TOL, (s_, rel_l2(gt[s_], rt))
+        # samples no window reads are exact zeros
+        read = np.zeros(wl.x.shape[1], bool)
+        for (t0, n, m, r) in ref:
+            read[max(0, t0 - (L - 1)):t0 + n] = True
+        assert np.all(gx[s_][~read] == 0)
