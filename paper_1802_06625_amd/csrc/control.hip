@@ -750,31 +750,54 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
+// Phase 2 of the batch bookkeeping.  Workgroup (actor a, task t); the tasks
+// of an actor are independent (each reads only phase-1 outputs and each
+// counter has one writer task):
+//   t = 0  firing numbers, queue/control-FIFO bases, firing counters;
+//   t = 1  work-list region of the actor's data kernel (filter-bank tiles or
+//          copy items) and per-iteration offsets in it;
+//   t = 2  sink output offsets;
+//   t = 3  branch statistics of a filter bank;
+//   t >= kScanFixed  one FIFO access: scan of its per-iteration counts, the
+//          FIFO's index and token counters, max occupancy.
+constexpr uint32_t kScanFixed = 4;
 __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b) {
   __shared__ uint32_t sh[kScanNT * kScanE];
   __shared__ uint32_t sm32[32];
   __shared__ unsigned long long sm64[32];
   __shared__ unsigned long long s_bf[PRUNE_MAX_BRANCHES], s_bt[PRUNE_MAX_BRANCHES];
   __shared__ uint32_t s_res;
-  const uint32_t a = blockIdx.x;
+  const uint32_t a = blockIdx.x, task = blockIdx.y;
   const uint32_t B = c.B, Bc = c.Bcap, tid = threadIdx.x, nt = blockDim.x;
   ActorDev &A = c.actors[a];
   const uint32_t kind = A.kind;
   const size_t o = (size_t)a * Bc;
   // sources, configuration actors and dynamic actors fire every iteration
   const bool always = kind == PRUNE_SOURCE || kind == PRUNE_CONFIG || A.cport_fifo != kNone;
-  uint32_t nf = B;
-  if (always) {
-    for (uint32_t i = tid; i < B; i += nt) b.s_firing[o + i] = i;
-  } else {
-    nf = chunk_scan(b.s_fired + o, b.s_firing + o, B, true, 0, nullptr, sh, sm32, sm64);
+
+  if (task == 0) {
+    uint32_t nf = B;
+    if (always) {
+      for (uint32_t i = tid; i < B; i += nt) b.s_firing[o + i] = i;
+    } else {
+      nf = chunk_scan(b.s_fired + o, b.s_firing + o, B, true, 0, nullptr, sh, sm32, sm64);
+    }
+    if (tid == 0) {
+      b.s_qbase[a] = (kind == PRUNE_SOURCE || kind == PRUNE_CONFIG) ? A.q_head
+                     : (A.cport_fifo != kNone ? c.fifos[A.cport_fifo].reads : 0);
+      A.firings += nf;
+      if (kind == PRUNE_SOURCE || kind == PRUNE_CONFIG) A.q_head += B;
+      if (A.cport_fifo != kNone) {
+        c.fifos[A.cport_fifo].reads += nf;
+        c.fifos[A.cport_fifo].tokens_read += nf;
+      }
+    }
+    return;
   }
-  if (tid == 0) {
-    b.s_qbase[a] = (kind == PRUNE_SOURCE || kind == PRUNE_CONFIG) ? A.q_head
-                   : (A.cport_fifo != kNone ? c.fifos[A.cport_fifo].reads : 0);
-    b.s_sink[a] = A.sink_pos;
-  }
-  for (uint32_t k2 = b.acc_off[a]; k2 < b.acc_off[a + 1]; ++k2) {
+
+  if (task >= kScanFixed) {
+    const uint32_t k2 = b.acc_off[a] + (task - kScanFixed);
+    if (k2 >= b.acc_off[a + 1]) return;
     const AccDev ac = b.acc[k2];
     FifoDev &f = c.fifos[ac.fifo];
     const uint32_t *cnt = b.s_cnt + (size_t)k2 * Bc;
@@ -809,18 +832,14 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
         if (occ > f.max_occ) f.max_occ = occ;
       }
     }
+    return;
   }
-  if (tid == 0) {
-    A.firings += nf;
-    if (kind == PRUNE_SOURCE || kind == PRUNE_CONFIG) A.q_head += B;
-    if (A.cport_fifo != kNone) {
-      c.fifos[A.cport_fifo].reads += nf;
-      c.fifos[A.cport_fifo].tokens_read += nf;
-    }
-  }
-  const uint32_t lev = c.level_of[a];
-  if (kind == PRUNE_FILTERBANK || kind == PRUNE_SWITCH || kind == PRUNE_SELECT ||
-      kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK) {
+
+  if (task == 1) {
+    if (!(kind == PRUNE_FILTERBANK || kind == PRUNE_SWITCH || kind == PRUNE_SELECT ||
+          kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK))
+      return;
+    const uint32_t lev = c.level_of[a];
     const bool fbk = kind == PRUNE_FILTERBANK;
     // total first, then the region, then the offsets
     uint32_t loc = 0;
@@ -830,12 +849,19 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
     __syncthreads();
     const uint32_t base = (fbk ? c.fb_item_off[lev] : c.copy_item_off[lev]) + s_res;
     chunk_scan(b.s_aux + o, b.s_auxoff + o, B, false, base, nullptr, sh, sm32, sm64);
+    return;
   }
-  if (kind == PRUNE_SINK && A.sink_out) {
+
+  if (task == 2) {
+    if (tid == 0) b.s_sink[a] = A.sink_pos;
+    if (!(kind == PRUNE_SINK && A.sink_out)) return;
+    __syncthreads();   // the sink base is read before it advances
     const uint32_t tot = chunk_scan(b.s_aux2 + o, b.s_aux2 + o, B, false, 0, nullptr, sh, sm32, sm64);
     if (tid == 0) A.sink_pos += tot;
+    return;
   }
-  if (kind == PRUNE_FILTERBANK) {
+
+  if (task == 3 && kind == PRUNE_FILTERBANK) {
     // branch statistics: per-thread counts in registers, wave sums, then
     // one shared-memory add per wave and branch
     const FbParamsDev &fb = c.fbs[A.fb];
@@ -1050,7 +1076,7 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
 void launch_batch(const CtrlArgs &c, const BatchArgs &b, uint32_t n_comp, uint32_t n_actors,
                   hipStream_t s) {
   hipLaunchKernelGGL(k_batch_decode, dim3((c.B + 255) / 256, n_comp), dim3(256), 0, s, c, b);
-  hipLaunchKernelGGL(k_batch_scan, dim3(n_actors), dim3(kScanNT), 0, s, c, b);
+  hipLaunchKernelGGL(k_batch_scan, dim3(n_actors, kScanFixed + b.max_acc), dim3(kScanNT), 0, s, c, b);
   hipLaunchKernelGGL(k_batch_emit, dim3((c.B + 63) / 64, n_actors), dim3(64), 0, s, c, b);
 }
 

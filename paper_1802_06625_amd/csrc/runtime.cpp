@@ -658,11 +658,14 @@ prune_status alloc_scratch(prune_graph *g) {
     }
   }
   acc_off[na] = (uint32_t)acc.size();
+  uint32_t max_acc = 0;
+  for (uint32_t a = 0; a < na; ++a) max_acc = std::max(max_acc, acc_off[a + 1] - acc_off[a]);
   std::vector<uint32_t> fifo_wacc(g->fifos.size(), 0);
   for (uint32_t k = 0; k < acc.size(); ++k)
     if (acc[k].dir == PRUNE_OUT) fifo_wacc[acc[k].fifo] = k;
   const size_t nacc = acc.size();
   BatchArgs &b = g->bargs;
+  b.max_acc = max_acc;
   TRY(upload(g, (uint32_t **)&b.acc_off, acc_off));
   TRY(upload(g, (AccDev **)&b.acc, acc));
   uint32_t **soa[] = {&b.s_fired, &b.s_mask, &b.s_rate, &b.s_bitmap, &b.s_firing, &b.s_aux,

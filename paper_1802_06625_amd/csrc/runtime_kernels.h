@@ -75,6 +75,7 @@ struct BatchArgs {
   uint64_t *s_sink;            // [n_actors] sink output offset at batch start
   uint64_t *s_rsnap;           // [n_fifos] tokens read before the batch
   const uint32_t *fifo_wacc;   // [n_fifos] index of the FIFO's writer access
+  uint32_t max_acc;            // most accesses of any actor (scan grid)
 };
 
 void launch_batch(const CtrlArgs &c, const BatchArgs &b, uint32_t n_comp, uint32_t n_actors,
