@@ -108,6 +108,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
   __shared__ uint32_t s_item;
   const uint32_t ni = *n_items;
   const int H = (int)Lmax - 1;
+  // the conjugate-tap table in LDS is kept while consecutive items share it
+  const float2 *tab_taps = nullptr;
+  uint32_t tab_key = 0xffffffffu;
   const uint32_t nh = H > 0 ? d.n_frames : 0u;
   for (;;) {
     if (t == 0) s_item = atomicAdd(ticket, 1u);
@@ -161,9 +164,12 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
       const int KH = 32 - __clz(bmask);
       const int L = (int)d.L[bank];
       const int S = (L + 15 + 3) / 4;
-      __syncthreads();   // s_g written; earlier readers of s_h done
       const float2 *tb = F.taps + (size_t)bank * d.Kmax * Lmax;
-      {
+      const uint32_t key = bmask | ((uint32_t)L << 16) | (bank << 24);
+      __syncthreads();   // s_g written; earlier readers of s_h done
+      if (tb != tab_taps || key != tab_key) {   // uniform across the workgroup
+        tab_taps = tb;
+        tab_key = key;
         constexpr int NIT = (kMKH * kHQ + kWG - 1) / kWG;
         float2 hv[NIT];
 #pragma unroll
@@ -243,18 +249,26 @@ constexpr int kUMax = 5;                     // units per wave: 5 slabs x 4 bran
 constexpr int kWX = kBT + PRUNE_MAX_L + 16;  // basis-plane positions per tile
 constexpr int kMaxRun = 8;                   // tiles accumulated before the diagonal sums
 
-// One unit's contribution of one tile: 16 steps of 4 blocks.
-//  gb: g-plane index of A(row li, block lk); ub: u-plane index of
-//  B(block lk, column li of the unit's slab).
+// The contributions of one tile to NU units of this wave: 16 steps of 4
+// blocks.  The A operand (cotangent) is the same for every unit, so each
+// step loads it once and issues 3 NU independent products.
+//  gb: g-plane index of A(row li, block lk); ub[k]: u-plane offset (plane
+//  and column) of B(block lk, column li of unit k's slab).
+template <int NU>
 __device__ __forceinline__ void gh_tile(const float4 *__restrict__ gp, const float2 *__restrict__ up,
-                                        int gb, int ub, floatx4 (&acc)[3]) {
+                                        int gb, const int *ub, floatx4 (*acc)[3]) {
 #pragma unroll
   for (int s = 0; s < kBT / 64; ++s) {
     const float4 gv = gp[gb + 64 * s];
-    const float2 uv = up[ub + 64 * s];
-    acc[0] = mfma4(gv.x, uv.x, acc[0]);
-    acc[1] = mfma4(gv.y, uv.y, acc[1]);
-    acc[2] = mfma4(gv.z, uv.x + uv.y, acc[2]);
+    float2 uv[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) uv[k] = up[ub[k] + 64 * s];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      acc[k][0] = mfma4(gv.x, uv[k].x, acc[k][0]);
+      acc[k][1] = mfma4(gv.y, uv[k].y, acc[k][1]);
+      acc[k][2] = mfma4(gv.z, uv[k].x + uv[k].y, acc[k][2]);
+    }
   }
 }
 }  // namespace
@@ -321,6 +335,26 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
         const int MT = (L + 15 + 15) / 16;
         __syncthreads();   // earlier readers of s_pd are done
         for (int k = t; k < kMKH * 2 * PRUNE_MAX_L; k += kWG) (&s_pd[0][0][0])[k] = make_float2(0.f, 0.f);
+        // This thread's share of a tile's cotangent and inputs, loaded into
+        // registers one tile ahead: the loads of the next tile are in flight
+        // while the current one is on the matrix cores.
+        constexpr int NG = kBT / kWG, NX = (kWX + kWG - 1) / kWG;
+        float2 gv[NG], xv[NX];
+        auto load_tile = [&](uint32_t itx) {
+          const int n0 = (int)items[itx].tile * kBT;
+#pragma unroll
+          for (int i = 0; i < NG; ++i) {
+            const int k = t + i * kWG;
+            gv[i] = n0 + k < n ? F.g[n0 + k] : make_float2(0.f, 0.f);
+          }
+          // u-plane index k holds position n0 - (Lmax-1) + k
+#pragma unroll
+          for (int i = 0; i < NX; ++i) {
+            const int k = t + i * kWG, p = n0 - ((int)Lmax - 1) + k;
+            xv[i] = (k < kWX && p < n && p >= -(int)F.t0) ? F.x[p] : make_float2(0.f, 0.f);
+          }
+        };
+        load_tile(r0);
         for (int b0 = 0; b0 < KH; b0 += kGH) {
           const int nb = min(kGH, KH - b0);
           const int units = MT * nb;   // unit u: slab u / nb, branch b0 + u % nb
@@ -328,23 +362,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
 #pragma unroll
           for (int k = 0; k < kUMax; ++k) acc[k][0] = acc[k][1] = acc[k][2] = floatx4{0.f, 0.f, 0.f, 0.f};
           for (uint32_t it = r0; it < r1; ++it) {
-            const int n0 = (int)items[it].tile * kBT;
             __syncthreads();   // earlier readers of s_g / s_u are done
             {
-              // all of this thread's loads first, then the stores
-              constexpr int NG = kBT / kWG, NX = (kWX + kWG - 1) / kWG;
-              float2 gv[NG], xv[NX];
-#pragma unroll
-              for (int i = 0; i < NG; ++i) {
-                const int k = t + i * kWG;
-                gv[i] = n0 + k < n ? F.g[n0 + k] : make_float2(0.f, 0.f);
-              }
-              // u-plane index k holds position n0 - (Lmax-1) + k
-#pragma unroll
-              for (int i = 0; i < NX; ++i) {
-                const int k = t + i * kWG, p = n0 - ((int)Lmax - 1) + k;
-                xv[i] = (k < kWX && p < n && p >= -(int)F.t0) ? F.x[p] : make_float2(0.f, 0.f);
-              }
 #pragma unroll
               for (int i = 0; i < NG; ++i)
                 s_g[t + i * kWG] = make_float4(gv[i].x, gv[i].y, gv[i].x + gv[i].y, 0.f);
@@ -362,14 +381,30 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
                 }
               }
             }
+            // the next tile of this bank: the run's next one, else the run's
+            // first one for the next branch group
+            if (it + 1 < r1) load_tile(it + 1);
+            else if (b0 + kGH < KH) load_tile(r0);
             __syncthreads();
+            // this wave's units u = w + kNW k (slab u / nb, branch b0 + u % nb),
+            // all at once; an inactive branch's unit is computed and discarded
+            {
+              int ub[kUMax];
 #pragma unroll
-            for (int k = 0; k < kUMax; ++k) {
-              const int u = w + kNW * k;
-              if (u < units) {
+              for (int k = 0; k < kUMax; ++k) {
+                const int u = w + kNW * k;
                 const int mt = u / nb, j = u - mt * nb;
-                if ((bmask >> (b0 + j)) & 1u)
-                  gh_tile(s_g, s_u[j], 16 * lk + li, 16 * lk + 16 * mt + li + ((int)Lmax - L), acc[k]);
+                ub[k] = u < units ? j * kWX + 16 * lk + 16 * mt + li + ((int)Lmax - L) : 0;
+              }
+              const int nu = units > w ? (units - w + kNW - 1) / kNW : 0;
+              const int gb = 16 * lk + li;
+              switch (nu) {
+                case 1: gh_tile<1>(s_g, &s_u[0][0], gb, ub, acc); break;
+                case 2: gh_tile<2>(s_g, &s_u[0][0], gb, ub, acc); break;
+                case 3: gh_tile<3>(s_g, &s_u[0][0], gb, ub, acc); break;
+                case 4: gh_tile<4>(s_g, &s_u[0][0], gb, ub, acc); break;
+                case 5: gh_tile<5>(s_g, &s_u[0][0], gb, ub, acc); break;
+                default: break;
               }
             }
           }

@@ -102,6 +102,9 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
   __shared__ uint32_t s_item;
   const int t = threadIdx.x;
   const uint32_t n_items = *n_items_ptr;
+  // the coefficient table in LDS is kept while consecutive tiles share it
+  const float2 *tab_taps = nullptr;
+  uint32_t tab_key = 0xffffffffu;
 
   for (;;) {
     if (t == 0) s_item = atomicAdd(ticket, 1u);
@@ -163,11 +166,16 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
         }
       }
       const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
-      for (int k = t; k < KH * Lpad; k += WG) {
-        const int b = k / Lpad, l = k - b * Lpad;
-        float2 c = make_float2(0.f, 0.f);
-        if (((bmask >> b) & 1u) && l < L) c = tb[(size_t)b * d.Lmax + l];
-        coef[k] = c;
+      const uint32_t key = bmask | ((uint32_t)L << 16) | (bank << 24);
+      if (tb != tab_taps || key != tab_key) {   // uniform: same frame descriptor for all threads
+        tab_taps = tb;
+        tab_key = key;
+        for (int k = t; k < KH * Lpad; k += WG) {
+          const int b = k / Lpad, l = k - b * Lpad;
+          float2 c = make_float2(0.f, 0.f);
+          if (((bmask >> b) & 1u) && l < L) c = tb[(size_t)b * d.Lmax + l];
+          coef[k] = c;
+        }
       }
       __syncthreads();
       horner_dispatch<J>(KH, win, coef, Lpad, t, accr, acci);

@@ -122,6 +122,9 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const uint32_t n_items = *n_items_ptr;
+  // the tap table in LDS is kept while consecutive tiles share it
+  const float2 *tab_taps = nullptr;
+  uint32_t tab_key = 0xffffffffu;
 
   for (;;) {
     if (t == 0) s_item = atomicAdd(ticket, 1u);
@@ -186,13 +189,18 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
       const int KH = 32 - __clz(bmask);
       const int L = (int)d.L[bank];
       const int S = (L + 15 + 3) / 4;
-      __syncthreads();   // earlier readers of s_h are done
       const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
-      for (int k = t; k < KH * kHQ; k += WG) {
-        const int b = k / kHQ, l = k - b * kHQ - kHOff;
-        float2 h = make_float2(0.f, 0.f);
-        if (((bmask >> b) & 1u) && l >= 0 && l < L) h = tb[(size_t)b * d.Lmax + l];
-        s_h[k] = make_float4(h.x, h.y, h.x + h.y, 0.f);
+      const uint32_t key = bmask | ((uint32_t)L << 16) | (bank << 24);
+      if (tb != tab_taps || key != tab_key) {   // uniform across the workgroup
+        __syncthreads();   // earlier readers of s_h are done
+        tab_taps = tb;
+        tab_key = key;
+        for (int k = t; k < KH * kHQ; k += WG) {
+          const int b = k / kHQ, l = k - b * kHQ - kHOff;
+          float2 h = make_float2(0.f, 0.f);
+          if (((bmask >> b) & 1u) && l >= 0 && l < L) h = tb[(size_t)b * d.Lmax + l];
+          s_h[k] = make_float4(h.x, h.y, h.x + h.y, 0.f);
+        }
       }
       __syncthreads();
       // B(m, block li) of result tile j reads window index
