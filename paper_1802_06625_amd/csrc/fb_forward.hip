@@ -97,24 +97,70 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
                                                    unsigned int *__restrict__ ticket) {
   constexpr int T = J * WG;
   constexpr int WMAX = T + PRUNE_MAX_L - 1;
+  constexpr int NIT = (WMAX + WG - 1) / WG;   // window elements per thread
   __shared__ float4 win[WMAX + (WMAX >> 3) + 1];
   __shared__ float2 coef[kMaxKH * PRUNE_MAX_L];
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_next[2];
   const int t = threadIdx.x;
   const uint32_t n_items = *n_items_ptr;
   // the coefficient table in LDS is kept while consecutive tiles share it
   const float2 *tab_taps = nullptr;
   uint32_t tab_key = 0xffffffffu;
 
+  // Window elements k = t + i*WG of the window [n0-(Lpad-1), n0+T) of a tile:
+  // positions before the frame come from its halo, after it are zero.
+  auto load_window = [&](const FbFrameDesc &dd, int n0x, int Lpadx, float2 *v) {
+    const int WN = T + Lpadx - 1, Hx = (int)dd.Lmax - 1, nx = (int)dd.n;
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+      const int k = t + i * WG, p = n0x - (Lpadx - 1) + k;
+      v[i] = make_float2(0.f, 0.f);
+      if (k < WN) {
+        if (p >= 0) {
+          if (p < nx) v[i] = dd.x[p];
+        } else if (-p <= (int)dd.halo_valid) {
+          v[i] = dd.halo[Hx + p];
+        }
+      }
+    }
+  };
+  // The next tile's window (its first active bank) is loaded into registers
+  // while the current tile computes; pv_bank = -1 when nothing is prefetched.
+  float2 pv[NIT];
+  int pv_bank = -1;
+  auto prefetch = [&](uint32_t itx) {
+    pv_bank = -1;
+    if (itx >= n_items) return;
+    const WorkItem wx = items[itx];
+    const FbFrameDesc &dx = frames[wx.frame];
+    if (dx.route) return;
+    const uint32_t kf = dx.Kmax >= 32 ? 0xffffffffu : ((1u << dx.Kmax) - 1u);
+    for (uint32_t bank = 0; bank < dx.n_banks; ++bank) {
+      if ((dx.mask >> (bank * dx.Kmax)) & kf) {
+        const int Lp = ((int)dx.L[bank] + J - 1) / J * J;
+        load_window(dx, (int)wx.tile * T, Lp, pv);
+        pv_bank = (int)bank;
+        return;
+      }
+    }
+  };
+
+  if (t == 0) s_next[0] = atomicAdd(ticket, 1u);
+  __syncthreads();
+  uint32_t it = s_next[0];
+  uint32_t par = 0;
+  prefetch(it);
   for (;;) {
-    if (t == 0) s_item = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const uint32_t it = s_item;
     if (it >= n_items) break;
+    // the following ticket, read by all threads after this tile's first barrier
+    if (t == 0) s_next[par ^ 1u] = atomicAdd(ticket, 1u);
     const WorkItem wi = items[it];
     const FbFrameDesc &d = frames[wi.frame];
     const int n = (int)d.n;
     const int n0 = (int)wi.tile * T;
+    const int cur_bank = pv_bank;
+    bool fetched = false;
+    uint32_t it_next = 0;
 
     if (d.route) {
       // passthrough-routed frame: y = x over the tile
@@ -125,71 +171,69 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
           for (uint32_t o = 0; o < d.n_y; ++o) d.y[o][p] = v;
         }
       }
-      __syncthreads();
-      continue;
-    }
-
-    float accr[J], acci[J];
+    } else {
+      float accr[J], acci[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) accr[j] = acci[j] = 0.f;
-
-    const int Hd = (int)d.Lmax - 1;
-    const uint32_t kfull = d.Kmax >= 32 ? 0xffffffffu : ((1u << d.Kmax) - 1u);
-    for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
-      const uint32_t bmask = (d.mask >> (bank * d.Kmax)) & kfull;
-      if (!bmask) continue;
-      const int KH = 32 - __clz(bmask);
-      const int L = (int)d.L[bank];
-      const int Lpad = (L + J - 1) / J * J;
-      __syncthreads();
-      {
-        // all of this thread's loads first, then the stores (one memory latency)
-        constexpr int NIT = (T + PRUNE_MAX_L - 1 + WG - 1) / WG;
-        const int WN = T + Lpad - 1;
+      for (int j = 0; j < J; ++j) accr[j] = acci[j] = 0.f;
+      const uint32_t kfull = d.Kmax >= 32 ? 0xffffffffu : ((1u << d.Kmax) - 1u);
+      for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+        const uint32_t bmask = (d.mask >> (bank * d.Kmax)) & kfull;
+        if (!bmask) continue;
+        const int KH = 32 - __clz(bmask);
+        const int L = (int)d.L[bank];
+        const int Lpad = (L + J - 1) / J * J;
         float2 v[NIT];
+        if ((int)bank == cur_bank) {
 #pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-          const int k = t + i * WG, p = n0 - (Lpad - 1) + k;
-          v[i] = make_float2(0.f, 0.f);
-          if (k < WN) {
-            if (p >= 0) {
-              if (p < n) v[i] = d.x[p];
-            } else if (-p <= (int)d.halo_valid) {
-              v[i] = d.halo[Hd + p];
-            }
+          for (int i = 0; i < NIT; ++i) v[i] = pv[i];
+        } else {
+          load_window(d, n0, Lpad, v);
+        }
+        __syncthreads();   // earlier readers of win / coef are done
+        {
+          const int WN = T + Lpad - 1;
+#pragma unroll
+          for (int i = 0; i < NIT; ++i) {
+            const int k = t + i * WG;
+            if (k < WN) win[pidx(k)] = make_float4(v[i].x, v[i].y, sqrtf(v[i].x * v[i].x + v[i].y * v[i].y), 0.f);
           }
         }
-#pragma unroll
-        for (int i = 0; i < NIT; ++i) {
-          const int k = t + i * WG;
-          if (k < WN) win[pidx(k)] = make_float4(v[i].x, v[i].y, sqrtf(v[i].x * v[i].x + v[i].y * v[i].y), 0.f);
+        const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
+        const uint32_t key = bmask | ((uint32_t)L << 16) | (bank << 24);
+        if (tb != tab_taps || key != tab_key) {   // uniform: same frame descriptor for all threads
+          tab_taps = tb;
+          tab_key = key;
+          for (int k = t; k < KH * Lpad; k += WG) {
+            const int b = k / Lpad, l = k - b * Lpad;
+            float2 c = make_float2(0.f, 0.f);
+            if (((bmask >> b) & 1u) && l < L) c = tb[(size_t)b * d.Lmax + l];
+            coef[k] = c;
+          }
         }
-      }
-      const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
-      const uint32_t key = bmask | ((uint32_t)L << 16) | (bank << 24);
-      if (tb != tab_taps || key != tab_key) {   // uniform: same frame descriptor for all threads
-        tab_taps = tb;
-        tab_key = key;
-        for (int k = t; k < KH * Lpad; k += WG) {
-          const int b = k / Lpad, l = k - b * Lpad;
-          float2 c = make_float2(0.f, 0.f);
-          if (((bmask >> b) & 1u) && l < L) c = tb[(size_t)b * d.Lmax + l];
-          coef[k] = c;
+        __syncthreads();
+        if (!fetched) {
+          fetched = true;
+          it_next = s_next[par ^ 1u];
+          prefetch(it_next);   // in flight during the compute below
         }
+        horner_dispatch<J>(KH, win, coef, Lpad, t, accr, acci);
       }
-      __syncthreads();
-      horner_dispatch<J>(KH, win, coef, Lpad, t, accr, acci);
-    }
-
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int p = n0 + t * J + j;
-      if (p < n) {
-        const float2 v = make_float2(accr[j], acci[j]);
-        for (uint32_t o = 0; o < d.n_y; ++o) d.y[o][p] = v;
+      for (int j = 0; j < J; ++j) {
+        const int p = n0 + t * J + j;
+        if (p < n) {
+          const float2 v = make_float2(accr[j], acci[j]);
+          for (uint32_t o = 0; o < d.n_y; ++o) d.y[o][p] = v;
+        }
       }
     }
     __syncthreads();
+    if (!fetched) {
+      it_next = s_next[par ^ 1u];
+      prefetch(it_next);
+    }
+    it = it_next;
+    par ^= 1u;
   }
 }
 
