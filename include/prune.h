@@ -335,11 +335,22 @@ typedef struct {
 /* y = filter bank of x (the forward of the merged DPG over whole streams,
  * including passthrough-routed frames).  x, y: device [S][N] complex64;
  * taps: device [S][n_banks][Kmax][Lmax] complex64; frames: device array.
- * The frames of one stream are consecutive in the array, in increasing t0,
- * and do not overlap; samples of y outside every frame are not written.
+ * Frames are sorted by stream, then by t0, and the frames of a stream do not
+ * overlap; samples of y outside every frame are not written.  A frame whose
+ * stream, extent or length is out of range is skipped (nothing of it is
+ * written); prune_fb_check_frames reports such frames.
  * E_UNSUPPORTED beyond the limits, E_ARG on inconsistent descriptors. */
 prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const void *taps,
                               const void *frames, void *y, prune_stream_t stream);
+
+/* Validate a device frame table against `desc` (synchronous on `stream`):
+ * *n_bad = number of frames with a stream index >= n_streams, t0 + n beyond
+ * stream_len, n > max_frame_len, or that break the order (a frame of a lower
+ * stream after a higher one, or overlapping / preceding the previous frame of
+ * its stream).  The filter-bank operations skip out-of-range frames and
+ * assume the order. */
+prune_status prune_fb_check_frames(const prune_fb_desc *desc, const void *frames, uint32_t *n_bad,
+                                   prune_stream_t stream);
 
 /* Bytes of device workspace prune_fb_backward needs for `desc`. */
 prune_status prune_fb_workspace_bytes(const prune_fb_desc *desc, size_t *bytes);

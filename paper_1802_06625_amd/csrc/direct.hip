@@ -102,6 +102,20 @@ __global__ __launch_bounds__(1024) void k_direct_prep(prune_fb_desc d, const flo
   }
 }
 
+// One thread per frame: out-of-range frames and order violations.
+__global__ __launch_bounds__(256) void k_check_frames(prune_fb_desc d, const prune_fb_frame *fr,
+                                                      uint32_t *n_bad) {
+  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= d.n_frames) return;
+  const prune_fb_frame q = fr[f];
+  bool bad = q.stream >= d.n_streams || (uint64_t)q.t0 + q.n > d.stream_len || q.n > d.max_frame_len;
+  if (f > 0) {
+    const prune_fb_frame p = fr[f - 1];
+    if (p.stream > q.stream || (p.stream == q.stream && (uint64_t)p.t0 + p.n > q.t0)) bad = true;
+  }
+  if (bad) atomicAdd(n_bad, 1u);
+}
+
 void launch_direct_prep(const prune_fb_desc &d, const float2 *x, const float2 *taps,
                         const prune_fb_frame *frames, float2 *y, uint32_t tile, FbFrameDesc *desc,
                         WorkItem *items, uint32_t *n_items, unsigned int *ticket, uint32_t *err,
@@ -213,6 +227,27 @@ prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const vo
   for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
   const int v = choose_variant(Lmax, desc->Kmax, desc->max_frame_len);
   return prune_fb_forward_variant(desc, x, taps, frames, y, v, stream);
+}
+
+prune_status prune_fb_check_frames(const prune_fb_desc *desc, const void *frames, uint32_t *n_bad,
+                                   prune_stream_t stream) {
+  if (!desc || !n_bad || (desc->n_frames && !frames)) return PRUNE_E_ARG;
+  *n_bad = 0;
+  if (desc->n_frames == 0) return PRUNE_OK;
+  uint32_t *d_bad = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMalloc((void **)&d_bad, sizeof(uint32_t)) != hipSuccess) return PRUNE_E_HIP;
+  prune_status st = PRUNE_OK;
+  if (hipMemsetAsync(d_bad, 0, sizeof(uint32_t), s) != hipSuccess) st = PRUNE_E_HIP;
+  if (st == PRUNE_OK) {
+    hipLaunchKernelGGL(k_check_frames, dim3((desc->n_frames + 255) / 256), dim3(256), 0, s, *desc,
+                       (const prune_fb_frame *)frames, d_bad);
+    if (hipMemcpyAsync(n_bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = PRUNE_E_HIP;
+  }
+  (void)hipFree(d_bad);
+  return st;
 }
 
 prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant) {

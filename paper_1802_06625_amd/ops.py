@@ -76,6 +76,16 @@ def fb_forward(x, taps, frames_dev, Kmax, bank_L, max_frame_len, y=None):
     return y
 
 
+def check_frames(frames_dev, n_streams, stream_len, Kmax, bank_L, max_frame_len):
+    """Number of frames the filter-bank operations would skip or that break
+    the required order (sorted by stream, then t0, no overlap)."""
+    d = make_desc(n_streams, stream_len, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
+    bad = C.c_uint32()
+    call("prune_fb_check_frames", C.byref(d), C.c_void_p(frames_dev.data_ptr()), C.byref(bad),
+         _stream())
+    return bad.value
+
+
 def workspace_bytes(S, N, Kmax, bank_L, n_frames, max_frame_len):
     d = make_desc(S, N, Kmax, bank_L, n_frames, max_frame_len)
     ws = C.c_size_t()

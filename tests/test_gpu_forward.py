@@ -182,3 +182,24 @@ def test_full_size_c5_sampled_frames(variant):
     wl = synth.make("C5")
     y, rows = _device_forward(wl, variant)
     _sampled_frames(wl, y, rows, 8)
+
+
+def test_check_frames_counts_violations():
+    """prune_fb_check_frames: valid tables report 0; each out-of-range or
+    out-of-order frame counts once."""
+    announce("check frames")
+    S, N, mfl = 2, 1000, 300
+    good = [(0, 0, 300, 1, 0), (0, 300, 200, 1, 0), (0, 600, 100, 1, 1), (1, 5, 300, 3, 0)]
+    assert ops.check_frames(ops.frame_table(good), S, N, 4, (8,), mfl) == 0
+    bad = [(0, 0, 300, 1, 0),
+           (0, 250, 100, 1, 0),    # overlaps the previous frame of its stream
+           (2, 0, 10, 1, 0),       # stream out of range
+           (1, 950, 100, 1, 0),    # runs past the stream end
+           (1, 0, 301, 1, 0),      # longer than max_frame_len, and before the previous frame
+           (0, 700, 10, 1, 0)]     # a lower stream after a higher one
+    assert ops.check_frames(ops.frame_table(bad), S, N, 4, (8,), mfl) == 5
+    for name in ["C3", "C5"]:
+        wl = synth.scaled(name)
+        rows = _frames(wl)
+        assert ops.check_frames(ops.frame_table(rows), wl.n_streams, wl.x.shape[1], wl.Kmax,
+                                wl.bank_L, int(wl.side[:, :, 1].max())) == 0
