@@ -15,8 +15,9 @@
 // Data layout: frames are complex64 (float2) blocks in HBM.  A work item is
 // one tile of T = J*WG consecutive outputs of one frame.  The tile's input
 // window [n0 - (Lpad-1), n0 + T) is staged in LDS as float4 {re, im, r, 0}
-// with one pad float4 per 8 (lane t reads at stride 9 float4, which maps 16
-// lanes onto 64 distinct banks).  Window positions before the frame come from
+// with one pad float4 per J (lane t reads at stride J+1 float4, which puts the
+// 16 lanes of a 128-bit read in distinct banks, and makes every window and
+// coefficient read of a chunk a constant offset from one base).  Window positions before the frame come from
 // the frame's halo (the stream's past samples), positions after the frame
 // are zero.  Each lane computes J consecutive outputs from a register window
 // of 2J-1 samples per chunk of J taps; the tap coefficients of the chunk are
@@ -26,29 +27,41 @@
 
 namespace prune {
 
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+constexpr int kMaxKH = 10;
 
+// Window layout: one pad float4 per J, so position t*J + k (k >= 0) is at
+// t*(J+1) + k + k/J: a per-lane part plus a part uniform across lanes.  Lanes
+// read 16-byte elements J+1 apart (80 or 144 bytes), which puts the 16 lanes
+// of a 128-bit read in distinct banks.
+template <int J>
+__device__ __forceinline__ int pidx(int i) { return i + i / J; }
+
+// Coefficient table layout: tap-major, coef[l * kMaxKH + b], so the
+// coefficients of a chunk are at constant offsets from one base.
 template <int KH, int J>
 __device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
                                             const float2 *__restrict__ coef, int Lpad,
                                             int t, float *accr, float *acci) {
   const int nchunks = Lpad / J;
+  const float4 *wl = win + t * (J + 1);   // this lane's part of the window index
   for (int c = 0; c < nchunks; ++c) {
-    const int base = t * J + (Lpad - c * J - J);
+    // window positions t*J + k0 + w, k0 = Lpad - (c+1) J (a multiple of J)
+    const int k0 = Lpad - c * J - J;
+    const float4 *wb = wl + k0 + k0 / J;
+    const float2 *cb = coef + c * J * kMaxKH;
     float xr[2 * J - 1], xi[2 * J - 1], rr[2 * J - 1];
 #pragma unroll
     for (int w = 0; w < 2 * J - 1; ++w) {
-      const float4 v = win[pidx(base + w)];
+      const float4 v = wb[w + w / J];
       xr[w] = v.x;
       xi[w] = v.y;
       rr[w] = v.z;
     }
 #pragma unroll
     for (int i = 0; i < J; ++i) {
-      const int l = c * J + i;
       float2 cf[KH];
 #pragma unroll
-      for (int b = 0; b < KH; ++b) cf[b] = coef[b * Lpad + l];
+      for (int b = 0; b < KH; ++b) cf[b] = cb[i * kMaxKH + b];
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         const int w = j - i + J - 1;
@@ -84,8 +97,6 @@ __device__ __forceinline__ void horner_dispatch(int KH, const float4 *win, const
   }
 }
 
-constexpr int kMaxKH = 10;
-
 // Persistent forward kernel: workgroups take tiles from the item list with an
 // atomic ticket until the list is exhausted.  *ticket must be zero at launch
 // (the producer of the item list clears it).
@@ -98,7 +109,7 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
   constexpr int T = J * WG;
   constexpr int WMAX = T + PRUNE_MAX_L - 1;
   constexpr int NIT = (WMAX + WG - 1) / WG;   // window elements per thread
-  __shared__ float4 win[WMAX + (WMAX >> 3) + 1];
+  __shared__ float4 win[WMAX + WMAX / J + 1];
   __shared__ float2 coef[kMaxKH * PRUNE_MAX_L];
   __shared__ uint32_t s_next[2];
   const int t = threadIdx.x;
@@ -195,7 +206,7 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
 #pragma unroll
           for (int i = 0; i < NIT; ++i) {
             const int k = t + i * WG;
-            if (k < WN) win[pidx(k)] = make_float4(v[i].x, v[i].y, sqrtf(v[i].x * v[i].x + v[i].y * v[i].y), 0.f);
+            if (k < WN) win[pidx<J>(k)] = make_float4(v[i].x, v[i].y, sqrtf(v[i].x * v[i].x + v[i].y * v[i].y), 0.f);
           }
         }
         const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
@@ -207,7 +218,7 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
             const int b = k / Lpad, l = k - b * Lpad;
             float2 c = make_float2(0.f, 0.f);
             if (((bmask >> b) & 1u) && l < L) c = tb[(size_t)b * d.Lmax + l];
-            coef[k] = c;
+            coef[l * kMaxKH + b] = c;
           }
         }
         __syncthreads();
