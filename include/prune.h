@@ -388,9 +388,11 @@ const char *prune_bwd_variant_name(int variant);
 /* Run the backward autotuner now for (L, K, n) and report the chosen form. */
 prune_status prune_autotune_bwd(uint32_t L, uint32_t K, uint32_t n, int *variant);
 
-/* Device-side timing of the filter-bank kernel launches of the last
- * prune_graph_fire / prune_fb_forward call on this thread (milliseconds,
- * measured with HIP events on the launch stream when timing is on). */
+/* Device-side timing of the filter-bank forward kernel launches made on this
+ * thread by prune_graph_fire (stream modes) and prune_fb_forward since
+ * timing was last switched on or off: HIP events recorded on the launch
+ * stream around each launch, summed (milliseconds) with the launch count.
+ * Autotuner launches and launches captured into hipGraphs are not timed. */
 prune_status prune_timing_enable(int on);
 prune_status prune_last_fb_kernel_ms(float *ms, uint32_t *launches);
 

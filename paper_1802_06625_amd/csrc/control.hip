@@ -877,15 +877,27 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
       unsigned long long bt[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) { bf[k] = 0; bt[k] = 0; }
-      for (uint32_t i = tid; i < B; i += nt) {
-        if (!b.s_fired[o + i]) continue;
-        const uint32_t bm = b.s_bitmap[o + i] >> d0;
-        const uint32_t n = cin[i] ? cin[i] - H : 0;
+      // four iterations' loads issued together, then accumulated
+      for (uint32_t i0 = tid; i0 < B; i0 += 4 * nt) {
+        uint32_t fz[4], bmv[4], cv[4];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint32_t on = (bm >> k) & 1u;
-          bf[k] += on;
-          bt[k] += on ? n : 0u;
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t i = i0 + q * nt;
+          const bool ok = i < B;
+          fz[q] = ok ? b.s_fired[o + i] : 0u;
+          bmv[q] = ok ? b.s_bitmap[o + i] : 0u;
+          cv[q] = ok ? cin[i] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t bm = fz[q] ? (bmv[q] >> d0) : 0u;
+          const uint32_t n = cv[q] ? cv[q] - H : 0u;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const uint32_t on = (bm >> k) & 1u;
+            bf[k] += on;
+            bt[k] += on ? n : 0u;
+          }
         }
       }
 #pragma unroll

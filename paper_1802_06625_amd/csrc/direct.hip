@@ -131,6 +131,7 @@ using namespace prune;
 namespace {
 
 std::mutex g_mu;
+thread_local bool g_tuning = false;   // autotuner launches are not timed
 struct DirectScratch {
   FbFrameDesc *desc = nullptr;
   WorkItem *items = nullptr;
@@ -201,9 +202,8 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
                      (float2 *)y, tile, sc->desc, sc->items, sc->ctr, sc->ctr + 1, sc->ctr + 2, s);
   const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 3, items);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const bool timed = timing_on();
+  const bool timed = timing_on() && !g_tuning;
   if (timed) {
-    timing_restart();
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, s);
@@ -316,6 +316,7 @@ int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   float best_ms = 1e30f;
+  g_tuning = true;
   for (int v = 1; v <= fb_variant_count(); ++v) {
     prune_fb_forward_variant(&d, x, t, fr, y, v, nullptr);   // warm-up
     (void)hipEventRecord(e0, nullptr);
@@ -329,6 +330,7 @@ int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
       best = v;
     }
   }
+  g_tuning = false;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(x); (void)hipFree(y); (void)hipFree(t); (void)hipFree(fr);

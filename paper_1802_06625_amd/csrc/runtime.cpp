@@ -1262,7 +1262,6 @@ prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings, p
   hipStream_t s = (hipStream_t)stream;
   for (uint32_t f = 0; f < g->fifos.size(); ++f)
     if (!g->fifos[f].storage) return fail(PRUNE_E_STATE, "fifo " + std::to_string(f) + " has no storage");
-  if (g_timing) timing_reset();
   uint64_t done = 0;
   if (mode == PRUNE_PER_FIRING) {
     for (;;) {
