@@ -112,8 +112,10 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
   const float2 *tab_taps = nullptr;
   uint32_t tab_key = 0xffffffffu;
   const uint32_t nh = H > 0 ? d.n_frames : 0u;
+  bool first = true;   // first item by workgroup index, later ones by ticket
   for (;;) {
-    if (t == 0) s_item = atomicAdd(ticket, 1u);
+    if (t == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(ticket, 1u);
+    first = false;
     __syncthreads();
     const uint32_t it = s_item;
     __syncthreads();   // s_item is rewritten by the next ticket
@@ -301,8 +303,10 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
   const uint32_t ng = (ni + R - 1) / R;
   const uint32_t kfull = (1u << d.Kmax) - 1u;
   __shared__ uint32_t s_grp;
+  bool first = true;   // first run group by workgroup index, later ones by ticket
   for (;;) {
-    if (t == 0) s_grp = atomicAdd(ticket, 1u);
+    if (t == 0) s_grp = first ? blockIdx.x : gridDim.x + atomicAdd(ticket, 1u);
+    first = false;
     __syncthreads();
     const uint32_t grp = s_grp;
     __syncthreads();   // s_grp is rewritten by the next ticket

@@ -97,9 +97,10 @@ __device__ __forceinline__ void horner_dispatch(int KH, const float4 *win, const
   }
 }
 
-// Persistent forward kernel: workgroups take tiles from the item list with an
-// atomic ticket until the list is exhausted.  *ticket must be zero at launch
-// (the producer of the item list clears it).
+// Persistent forward kernel: each workgroup takes tile blockIdx.x, then
+// further tiles from the item list with an atomic ticket (offset by the grid
+// size) until the list is exhausted.  *ticket must be zero at launch (the
+// producer of the item list clears it).
 template <int J, int WG, int WAVES>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void k_fb_forward(const FbFrameDesc *__restrict__ frames,
@@ -156,15 +157,14 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
     }
   };
 
-  if (t == 0) s_next[0] = atomicAdd(ticket, 1u);
-  __syncthreads();
-  uint32_t it = s_next[0];
+  // first tile by workgroup index, later ones by ticket (offset by the grid)
+  uint32_t it = blockIdx.x;
   uint32_t par = 0;
   prefetch(it);
   for (;;) {
     if (it >= n_items) break;
     // the following ticket, read by all threads after this tile's first barrier
-    if (t == 0) s_next[par ^ 1u] = atomicAdd(ticket, 1u);
+    if (t == 0) s_next[par ^ 1u] = gridDim.x + atomicAdd(ticket, 1u);
     const WorkItem wi = items[it];
     const FbFrameDesc &d = frames[wi.frame];
     const int n = (int)d.n;

@@ -126,8 +126,10 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
   const float2 *tab_taps = nullptr;
   uint32_t tab_key = 0xffffffffu;
 
+  bool first = true;   // first tile by workgroup index, later ones by ticket
   for (;;) {
-    if (t == 0) s_item = atomicAdd(ticket, 1u);
+    if (t == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(ticket, 1u);
+    first = false;
     __syncthreads();
     const uint32_t it = s_item;
     if (it >= n_items) break;
