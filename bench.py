@@ -300,7 +300,7 @@ def bench_direct(name, steps, warmup):
         finally:
             ops.set_bwd_variant(0)
     by_variant = {}
-    if name == "C5":
+    if name in ("C4", "C5"):
         # every forward kernel forced in turn (vector Horner and matrix-core
         # block-Toeplitz), same launch configuration as the autotuned call
         for v, vname in enumerate(ops.variant_names(), start=1):
@@ -332,6 +332,7 @@ def bench_direct(name, steps, warmup):
         res["fwd_ms_by_variant"] = by_variant
         res["fwd_tflops_alg_by_variant"] = {k: round(f_fwd / (v * 1e-3) / 1e12, 2)
                                             for k, v in by_variant.items()}
+    if name == "C5":
         # matrix-core kernel (block-Toeplitz form): the fastest of its
         # variants, kernel duration from the library's HIP events on the
         # launch stream
