@@ -4,7 +4,9 @@ A plain, slow, sequential CPU implementation in float64 (numpy) of what the
 HIP library computes: the model of computation (graph, ports, FIFOs with the
 capacity of Eq. 2 and the delay access pattern of Fig. 6, control tokens
 decoded per Eq. 1, blocking firing rules, a round-robin scheduler with
-deadlock detection, per-firing logs), the memory-polynomial filter-bank actor
+deadlock detection, per-firing logs), the compile-time analysis of Sec. IV-V
+(design rules, DPGs and their dynamic components, per-component consistency
+and buffer bounds), the memory-polynomial filter-bank actor
 by its direct definition, its adjoint in closed form, finite differences and
 the least-squares / Adam fit.
 
@@ -22,6 +24,6 @@ from .moc import (PruneError, Graph, E_ARG, E_STATE, E_RATE_MISMATCH, E_PORT_KIN
                   FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK, POLY, FIR, ADD,
                   fifo_capacity, fifo_write_slot, fifo_read_slot)
 from .filterbank import (fb_frame, fb_stream, fb_stream_adjoint, basis)
-from . import graphs, fit
+from . import graphs, fit, analysis
 
 __all__ = [n for n in dir() if not n.startswith("_")]
