@@ -144,6 +144,7 @@ def main():
     pg = PlainGraph(wl.Kmax, wl.bank_L, n, F)
     g_variant = ops.autotuned_variant(Lt, wl.Kmax, n)
     g = pg.g
+    analysis = analysis_summary(g)
     g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
     pg.fifo_in.view(F, n).copy_(torch.from_numpy(wl.x[0]).view(F, n))
     del wl.x
@@ -206,7 +207,8 @@ def main():
                       "fb_variant": ops.variant_names()[g_variant - 1] if g_variant else None},
            "event_ms_per_step": round(ev_ms_step, 4),
            "batched_graph_msamples": round(samples / (graph_ms * 1e-3) / 1e6, 1),
-           "batched_stream_msamples": round(samples / (stream_ms * 1e-3) / 1e6, 1)}
+           "batched_stream_msamples": round(samples / (stream_ms * 1e-3) / 1e6, 1),
+           "analysis": analysis}
     if args.profile_only:
         print(json.dumps(out))
         return
@@ -362,6 +364,16 @@ def bench_direct(name, steps, warmup):
     return res
 
 
+def analysis_summary(g):
+    """Compile-time analysis of a workload graph (prune_graph_analyze, host
+    code): its size, what it found and how long it took."""
+    t0 = time.perf_counter()
+    rep = g.analyze()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"actors": len(rep["dc_of_actor"]), "fifos": len(rep["beta"]), "dpgs": len(rep["dpgs"]),
+            "dcs": len(rep["dcs"]), "violations": len(rep["violations"]), "ms": round(ms, 3)}
+
+
 def bench_c3(steps, warmup):
     """Batched uneven frames: 2048 frames with log-uniform rates in
     [256, 65536], three tap banks, one hipGraph replay per batch."""
@@ -418,6 +430,7 @@ def bench_c5(steps, warmup):
     S, F, n = wl.n_streams, wl.n_frames, int(wl.side[0, 0, 1])
     rg = RoutedGraph(S, wl.Kmax, wl.bank_L, n, F)
     g = rg.g
+    analysis = analysis_summary(g)
     for s, ids in enumerate(rg.streams):
         g.set_taps(ids["fb"], torch.from_numpy(wl.taps[s]).cuda())
         rg.storage[s]["in"].view(F, n).copy_(torch.from_numpy(wl.x[s]).view(F, n))
@@ -440,7 +453,8 @@ def bench_c5(steps, warmup):
            "mode": "batched_graph" if ms_graph <= ms_stream else "batched_stream",
            "graph_ms": round(ms_graph, 4), "stream_ms": round(ms_stream, 4),
            "tflops_alg": round(flops / (ms * 1e-3) / 1e12, 2),
-           "fb_variant": ops.variant_names()[ops.autotuned_variant(Lt, wl.Kmax, n) - 1]}
+           "fb_variant": ops.variant_names()[ops.autotuned_variant(Lt, wl.Kmax, n) - 1],
+           "analysis": analysis}
     del g, rg
     torch.cuda.empty_cache()
     return res

@@ -66,7 +66,10 @@ enum {
   PRUNE_E_DEADLOCK = -9,      /* no actor can fire while input is pending    */
   PRUNE_E_CAPACITY = -10,     /* bound storage smaller than Eq. 2's capacity */
   PRUNE_E_HIP = -11,          /* HIP runtime error (text in last_error)      */
-  PRUNE_E_UNSUPPORTED = -12   /* shape beyond the kernels' limits            */
+  PRUNE_E_UNSUPPORTED = -12,  /* shape beyond the kernels' limits            */
+  PRUNE_E_RULE = -13          /* design rule or DPG validity violated, or a
+                                 dynamic component that deadlocks (only with
+                                 PRUNE_CHECK_RULES, see prune_graph_analyze) */
 };
 
 enum { PRUNE_IN = 0, PRUNE_OUT = 1 };
@@ -226,6 +229,103 @@ prune_status prune_control_table_set(prune_graph_t g, prune_id ctrl_port, prune_
  * Allocates library-owned device state (counters, control FIFOs, histories,
  * taps, work lists).  Errors as listed with the status codes. */
 prune_status prune_graph_finalize(prune_graph_t g, uint32_t C);
+
+/* ---- compile-time analysis (Sec. IV design rules, Sec. V) --------------- */
+
+/* Checks that finalize runs.  PRUNE_CHECK_RULES: prune_graph_finalize runs
+ * prune_graph_analyze first and fails with E_RULE (the first violation in
+ * prune_last_error) if the analysis reports any violation.  Default: off,
+ * finalize applies the local checks only. */
+enum { PRUNE_CHECK_RULES = 1u };
+prune_status prune_graph_set_checks(prune_graph_t g, uint32_t flags);
+
+/* Violation codes of the analysis, with the meaning of the two subjects
+ * (a, b) of each record; -1 where unused.
+ *  RULE1      (1)  linked DRPs not controlled by one control output port
+ *                  and one element, T[p_q][p_x] = T[p_q][p_y] > 0 (Sec. IV,
+ *                  linked port control rule); a, b: the two DRP ports.
+ *  RULE2      (2)  one control output port reaches two dynamic actors
+ *                  through FIFOs of different delay (balanced delay rule);
+ *                  a: the lowest-id actor controlled by the port, b: the
+ *                  other actor.
+ *  RULE3_KIND (31) an actor on a connecting subchain is not a static
+ *                  processing actor (connecting subchain rule, part 1); a.
+ *  RULE3_SHARED (32) an actor lies on connecting subchains of two different
+ *                  dynamic-actor pairs (part 2); a.
+ *  RULE4      (4)  an actor with input and output DRPs (single-sided
+ *                  dynamism); a.
+ *  RULE5      (5)  an actor b next to a subchain through an SRP of b lies on
+ *                  no chain connecting the pair (encapsulation rule); a = b.
+ *  DPG_A      (10) a DC not attached to a DRP of both x and y (Sec. V,
+ *                  validity a); a: DPG index, b: DC index.
+ *  DPG_B_DC   (11) the DRPs attached to one DC use more than one element of
+ *                  the control value (validity b); a: DPG, b: DC.
+ *  DPG_B_COUNT (12) two DCs share an element, or the DRPs of x and y use a
+ *                  number of elements other than the DC count M; a: DPG.
+ *  DPG_C      (13) a FIFO with one end in a DC and the other not on a DRP of
+ *                  x or y (a DC is entered and left only through the DPG's
+ *                  DRPs); a: DPG, b: FIFO.
+ *  DEADLOCK_DC (20) the periodic schedule of a DC cannot complete (Sec. V:
+ *                  the DC, an SDF graph, is not consistent); a: DPG, b: DC.
+ *  DEADLOCK_TOP (21) the actors outside every DC cannot complete one
+ *                  period.
+ *  PAIRING    (40) a dynamic actor is linked to more than one partner; a.
+ *  UNPAIRED   (41) a dynamic actor belongs to no DPG; a. */
+enum {
+  PRUNE_RULE1 = 1, PRUNE_RULE2 = 2, PRUNE_RULE4 = 4, PRUNE_RULE5 = 5,
+  PRUNE_DPG_A = 10, PRUNE_DPG_B_DC = 11, PRUNE_DPG_B_COUNT = 12, PRUNE_DPG_C = 13,
+  PRUNE_DEADLOCK_DC = 20, PRUNE_DEADLOCK_TOP = 21,
+  PRUNE_RULE3_KIND = 31, PRUNE_RULE3_SHARED = 32,
+  PRUNE_PAIRING = 40, PRUNE_UNPAIRED = 41
+};
+
+typedef struct {
+  uint32_t n_linked;       /* linked DRP pairs                                */
+  uint32_t n_dpgs;         /* dynamic processing graphs                       */
+  uint32_t n_dcs;          /* dynamic components over all DPGs (M per DPG)    */
+  uint32_t n_violations;   /* 0 for a graph that passes every check           */
+} prune_analysis_counts;
+
+/* Analyse the graph as built so far (finalized or not; host-only graphs
+ * included; nothing runs on a device) and keep the report in the graph
+ * until the next call.  Adjacency and chains use data FIFOs (FIFOs into
+ * control ports are left out).  A dynamic actor is one with an external
+ * DRP: a filter bank, whose branch DRPs are internal, counts as a static
+ * processing actor here.  Each DPG is (q, x, y) with x the actor with
+ * output DRPs and y the actor with input DRPs of linked DRPs; its DCs are
+ * the components left after removing q, x and y (Sec. V procedure), plus
+ * one dummy DC per FIFO from a DRP of x to a DRP of y.  Each DC is scheduled
+ * once (x, its actors in increasing id, y, always the first fireable one;
+ * all repetition counts are one because a FIFO has one rate at both ends),
+ * which decides its deadlock freedom and gives the buffer bound beta(f) of
+ * each of its FIFOs: the largest token count over the initial state and the
+ * state after each firing.  The actors outside every DC and the FIFOs among
+ * them, control FIFOs included, are scheduled the same way in id order.
+ * counts may be NULL. */
+prune_status prune_graph_analyze(prune_graph_t g, prune_analysis_counts *counts);
+
+/* Tables of the last analysis, as int64 values (-1 = none):
+ *  PRUNE_AN_LINKED      2 per linked DRP pair: (p, p2), p < p2, sorted.
+ *  PRUNE_AN_DPGS        4 per DPG: (q, x, y, control output port of x), in
+ *                       increasing (x, y).
+ *  PRUNE_AN_DCS         4 per DC: (DPG index, control-value element (1-based;
+ *                       -1 if its DRPs disagree), FIFO of a dummy DC or -1,
+ *                       number of actors), DCs of a DPG in increasing
+ *                       smallest actor id, dummy DCs last in FIFO order.
+ *  PRUNE_AN_DC_ACTORS   the actors of every DC in DC order, each DC's sorted.
+ *  PRUNE_AN_ACTOR_DC    1 per actor: index of its DC, or -1.
+ *  PRUNE_AN_BETA        1 per FIFO: its buffer bound, or -1 where a schedule
+ *                       deadlocks or the FIFO joins a DC to an actor that is
+ *                       not x or y.
+ *  PRUNE_AN_VIOLATIONS  3 per violation: (code, a, b), sorted, unique.
+ * *n receives the number of values of the table; min(cap, *n) are copied to
+ * out (out may be NULL when cap is 0).  E_STATE before any analysis. */
+enum {
+  PRUNE_AN_LINKED = 0, PRUNE_AN_DPGS = 1, PRUNE_AN_DCS = 2, PRUNE_AN_DC_ACTORS = 3,
+  PRUNE_AN_ACTOR_DC = 4, PRUNE_AN_BETA = 5, PRUNE_AN_VIOLATIONS = 6
+};
+prune_status prune_graph_analysis_table(prune_graph_t g, int table, int64_t *out, size_t cap,
+                                        size_t *n);
 
 /* Bytes of storage FIFO `fifo` needs: B * Gamma_f of Eq. 2. */
 prune_status prune_fifo_required_bytes(prune_graph_t g, prune_id fifo, size_t *bytes);

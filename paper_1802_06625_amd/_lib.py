@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(HERE, "libprune_hip.so")
 OK = 0
 E_ARG, E_STATE, E_RATE_MISMATCH, E_PORT_KIND, E_RULE4, E_CONNECT = -1, -2, -3, -4, -5, -6
 E_DELAY, E_TOKEN, E_DEADLOCK, E_CAPACITY, E_HIP, E_UNSUPPORTED = -7, -8, -9, -10, -11, -12
+E_RULE = -13
+CHECK_RULES = 1
+AN_LINKED, AN_DPGS, AN_DCS, AN_DC_ACTORS, AN_ACTOR_DC, AN_BETA, AN_VIOLATIONS = range(7)
 IN, OUT = 0, 1
 SRP, DRP, CPORT = 0, 1, 2
 PORT_PARAM = 1
@@ -40,6 +43,11 @@ class ConfigParams(C.Structure):
 class FbParams(C.Structure):
     _fields_ = [("n_banks", C.c_uint32), ("Kmax", C.c_uint32), ("L", C.c_uint32 * MAX_BANKS),
                 ("windowed", C.c_uint32), ("fixed_mask", C.c_uint32)]
+
+
+class AnalysisCounts(C.Structure):
+    _fields_ = [("n_linked", C.c_uint32), ("n_dpgs", C.c_uint32), ("n_dcs", C.c_uint32),
+                ("n_violations", C.c_uint32)]
 
 
 class FifoStats(C.Structure):
@@ -77,6 +85,10 @@ SIGNATURES = [
     ("prune_fifo_connect", _ST, [_P, _ID, _ID, C.c_uint32, C.c_uint32, C.POINTER(_ID)]),
     ("prune_control_table_set", _ST, [_P, _ID, _ID, C.c_uint32]),
     ("prune_graph_finalize", _ST, [_P, C.c_uint32]),
+    ("prune_graph_set_checks", _ST, [_P, C.c_uint32]),
+    ("prune_graph_analyze", _ST, [_P, C.POINTER(AnalysisCounts)]),
+    ("prune_graph_analysis_table", _ST, [_P, C.c_int, C.POINTER(C.c_int64), C.c_size_t,
+                                         C.POINTER(C.c_size_t)]),
     ("prune_fifo_required_bytes", _ST, [_P, _ID, C.POINTER(C.c_size_t)]),
     ("prune_fifo_bind_storage", _ST, [_P, _ID, _P, C.c_size_t]),
     ("prune_fifo_write_window", _ST, [_P, _ID, C.c_uint32, C.POINTER(_P)]),

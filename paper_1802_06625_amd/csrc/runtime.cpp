@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "prune.h"
+#include "design_analysis.h"
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
@@ -115,6 +116,10 @@ struct prune_graph {
   std::vector<HPort> ports;
   std::vector<HFifo> fifos;
   std::map<std::pair<uint32_t, uint32_t>, uint32_t> table;
+  // compile-time analysis (Sec. IV-V)
+  uint32_t checks = 0;
+  bool analyzed = false;
+  prune::DesignReport report;
   // device tables
   FifoDev *d_fifos = nullptr;
   PortDev *d_ports = nullptr;
@@ -983,7 +988,79 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
 
 }  // namespace
 
+// The graph's structure as the compile-time analysis reads it.
+static void run_design_analysis(prune_graph *g) {
+  prune::DesignGraph d;
+  d.kind.reserve(g->actors.size());
+  for (const HActor &A : g->actors) {
+    d.kind.push_back(A.kind);
+    d.ports.push_back(A.ports);
+  }
+  d.port.reserve(g->ports.size());
+  for (const HPort &P : g->ports) d.port.push_back({P.actor, P.dir, P.kind, P.internal ? std::vector<uint32_t>{} : P.fifos});
+  d.fifo.reserve(g->fifos.size());
+  for (const HFifo &F : g->fifos) d.fifo.push_back({F.src, F.dst, F.rate, F.delay});
+  d.table = g->table;
+  g->report = prune::analyze_design(d);
+  g->analyzed = true;
+}
+
 extern "C" {
+
+prune_status prune_graph_set_checks(prune_graph_t g, uint32_t flags) {
+  if (!g) return fail(PRUNE_E_ARG, "null graph");
+  if (flags & ~(uint32_t)PRUNE_CHECK_RULES) return fail(PRUNE_E_ARG, "unknown check flags");
+  g->checks = flags;
+  return PRUNE_OK;
+}
+
+prune_status prune_graph_analyze(prune_graph_t g, prune_analysis_counts *counts) {
+  if (!g) return fail(PRUNE_E_ARG, "null graph");
+  run_design_analysis(g);
+  if (counts) {
+    counts->n_linked = (uint32_t)g->report.linked.size();
+    counts->n_dpgs = (uint32_t)g->report.dpgs.size();
+    counts->n_dcs = (uint32_t)g->report.dcs.size();
+    counts->n_violations = (uint32_t)g->report.violations.size();
+  }
+  return PRUNE_OK;
+}
+
+prune_status prune_graph_analysis_table(prune_graph_t g, int table, int64_t *out, size_t cap,
+                                        size_t *n) {
+  if (!g || !n || (cap && !out)) return fail(PRUNE_E_ARG, "null argument");
+  if (!g->analyzed) return fail(PRUNE_E_STATE, "no analysis yet");
+  const prune::DesignReport &R = g->report;
+  std::vector<int64_t> v;
+  switch (table) {
+    case PRUNE_AN_LINKED:
+      for (auto &e : R.linked) v.insert(v.end(), e.begin(), e.end());
+      break;
+    case PRUNE_AN_DPGS:
+      for (auto &e : R.dpgs) v.insert(v.end(), e.begin(), e.end());
+      break;
+    case PRUNE_AN_DCS:
+      for (auto &e : R.dcs) v.insert(v.end(), {e.dpg, e.element, e.direct_fifo, (int64_t)e.actors.size()});
+      break;
+    case PRUNE_AN_DC_ACTORS:
+      for (auto &e : R.dcs) v.insert(v.end(), e.actors.begin(), e.actors.end());
+      break;
+    case PRUNE_AN_ACTOR_DC:
+      v = R.dc_of_actor;
+      break;
+    case PRUNE_AN_BETA:
+      v = R.beta;
+      break;
+    case PRUNE_AN_VIOLATIONS:
+      for (auto &e : R.violations) v.insert(v.end(), e.begin(), e.end());
+      break;
+    default:
+      return fail(PRUNE_E_ARG, "unknown analysis table");
+  }
+  *n = v.size();
+  std::copy(v.begin(), v.begin() + std::min(cap, v.size()), out);
+  return PRUNE_OK;
+}
 
 prune_status prune_graph_create(int hip_device, prune_graph_t *out) {
   if (!out) return fail(PRUNE_E_ARG, "null output");
@@ -1106,6 +1183,15 @@ prune_status prune_control_table_set(prune_graph_t g, prune_id ctl, prune_id drp
 prune_status prune_graph_finalize(prune_graph_t g, uint32_t C) {
   TRY(check_graph(g, false));
   if (C == 0) return fail(PRUNE_E_ARG, "C must be positive");
+  if (g->checks & PRUNE_CHECK_RULES) {
+    run_design_analysis(g);
+    if (!g->report.violations.empty()) {
+      const auto &v = g->report.violations.front();
+      return fail(PRUNE_E_RULE, "design analysis: violation code " + std::to_string(v[0]) + " (" +
+                                    std::to_string(v[1]) + ", " + std::to_string(v[2]) + "), " +
+                                    std::to_string(g->report.violations.size()) + " in total");
+    }
+  }
   for (uint32_t p = 0; p < g->ports.size(); ++p) {
     const HPort &P = g->ports[p];
     if (P.internal) continue;
@@ -1480,6 +1566,7 @@ const char *prune_status_string(prune_status s) {
     case PRUNE_E_CAPACITY: return "PRUNE_E_CAPACITY";
     case PRUNE_E_HIP: return "PRUNE_E_HIP";
     case PRUNE_E_UNSUPPORTED: return "PRUNE_E_UNSUPPORTED";
+    case PRUNE_E_RULE: return "PRUNE_E_RULE";
     default: return "PRUNE_E_UNKNOWN";
   }
 }

@@ -79,8 +79,42 @@ class Graph:
     def control(self, ctl_port, drp, element):
         call("prune_control_table_set", self.h, ctl_port, drp, int(element))
 
-    def finalize(self, C_):
+    def finalize(self, C_, check_rules=False):
+        """Validate and size the graph; with check_rules the library runs the
+        compile-time analysis first and refuses a graph with violations."""
+        call("prune_graph_set_checks", self.h, L.CHECK_RULES if check_rules else 0)
         call("prune_graph_finalize", self.h, int(C_))
+
+    def _table(self, which):
+        n = C.c_size_t()
+        call("prune_graph_analysis_table", self.h, which, None, 0, C.byref(n))
+        buf = (C.c_int64 * max(n.value, 1))()
+        call("prune_graph_analysis_table", self.h, which, buf, n.value, C.byref(n))
+        return [int(v) for v in buf[:n.value]]
+
+    def analyze(self):
+        """Compile-time analysis of Sec. IV-V (prune_graph_analyze): linked DRP
+        pairs, DPGs (q, x, y, control port), DCs (dpg, element, actors,
+        direct FIFO), the DC of each actor, the buffer bound of each FIFO and
+        the sorted violations (code, a, b)."""
+        cnt = L.AnalysisCounts()
+        call("prune_graph_analyze", self.h, C.byref(cnt))
+        lk = self._table(L.AN_LINKED)
+        dp = self._table(L.AN_DPGS)
+        dc = self._table(L.AN_DCS)
+        acts = self._table(L.AN_DC_ACTORS)
+        vi = self._table(L.AN_VIOLATIONS)
+        dcs, k = [], 0
+        for i in range(0, len(dc), 4):
+            n = dc[i + 3]
+            dcs.append((dc[i], dc[i + 1], tuple(acts[k:k + n]), dc[i + 2]))
+            k += n
+        return {"linked": [tuple(lk[i:i + 2]) for i in range(0, len(lk), 2)],
+                "dpgs": [tuple(dp[i:i + 4]) for i in range(0, len(dp), 4)],
+                "dcs": dcs,
+                "dc_of_actor": self._table(L.AN_ACTOR_DC),
+                "beta": self._table(L.AN_BETA),
+                "violations": [tuple(vi[i:i + 3]) for i in range(0, len(vi), 3)]}
 
     # ---- storage and input ------------------------------------------------
     def required_bytes(self, fifo):
@@ -212,7 +246,7 @@ class PlainGraph:
         self.f_out = g.connect(p_out, p_snk, atr)
         for d in range(D):
             g.control(p_ctl, g.branch(self.fb, d), d + 1)
-        g.finalize(C_)
+        g.finalize(C_, check_rules=True)
         self.atr = atr
         self.fifo_in = g.alloc_fifo(self.f_in)
         self.fifo_out = g.alloc_fifo(self.f_out)
@@ -268,7 +302,7 @@ class RoutedGraph:
             g.control(p_ctl, p_sl1, 2)
             ids["fifos"] = f
             self.streams.append(ids)
-        g.finalize(C_)
+        g.finalize(C_, check_rules=True)
         self.atr = atr
         self.storage = []
         for ids in self.streams:
