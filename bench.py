@@ -119,7 +119,8 @@ def main():
         fn = {"c3": lambda: bench_c3(args.steps, args.warmup),
               "c4": lambda: bench_direct("C4", args.steps, args.warmup),
               "c5": lambda: bench_c5(args.steps, args.warmup),
-              "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup)}[args.only]
+              "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup),
+              "c2u": lambda: bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), None)}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     if args.copy_calib:
@@ -241,6 +242,8 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     if not args.only_c2:
+        print("bench: unfused DPD graph", file=sys.stderr, flush=True)
+        out["c2_unfused"] = bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), ms_step)
         print("bench: fwd+bwd (differentiation workload)", file=sys.stderr, flush=True)
         out["c4_fwd_bwd"] = bench_direct("C4", args.steps, args.warmup)
         print("bench: batched uneven frames", file=sys.stderr, flush=True)
@@ -372,6 +375,45 @@ def analysis_summary(g):
     ms = (time.perf_counter() - t0) * 1e3
     return {"actors": len(rep["dc_of_actor"]), "fifos": len(rep["beta"]), "dpgs": len(rep["dpgs"]),
             "dcs": len(rep["dcs"]), "violations": len(rep["violations"]), "ms": round(ms, 3)}
+
+
+def bench_c2_unfused(steps, warmup, fused_ms):
+    """The headline batch through the DPD graph before actor merging
+    (poly -> 10 FIR actors -> add, per-branch device FIFOs): what merging
+    the dynamic processing graph into one actor buys."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import UnfusedGraph
+    wl = synth.make("C2")
+    side = wl.side[0]
+    F, n = side.shape[0], int(side[0, 1])
+    ug = UnfusedGraph(wl.Kmax, wl.bank_L[0], n, F)
+    g = ug.g
+    ug.set_taps(torch.from_numpy(wl.taps[0, 0]).cuda())
+    ug.fifo_in.view(F, n).copy_(torch.from_numpy(wl.x[0]).view(F, n))
+    del wl.x
+    for _ in range(2 * (steps + warmup) + 1):
+        g.source_push(ug.src, None, side[:, 1])
+        g.config_push(ug.cfg, side)
+    torch.cuda.synchronize()
+    g.fire(L.BATCHED_GRAPH, F)
+    ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
+    ms_stream = _time_events(lambda: g.fire(L.BATCHED, F), steps, warmup)
+    g.sync()
+    ms = min(ms_graph, ms_stream)
+    samples = F * n
+    fifo_bytes = sum(g.required_bytes(f) for f in [ug.f_in, ug.f_out] + ug.f_win + ug.f_br)
+    res = {"workload": "the headline batch (4096 x 16384, K~U{1..10}, L=32) through the unfused "
+                       "DPD graph: poly -> 10 FIR_b -> add with per-branch device FIFOs",
+           "msamples": round(samples / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
+           "mode": "batched_graph" if ms_graph <= ms_stream else "batched_stream",
+           "graph_ms": round(ms_graph, 4), "stream_ms": round(ms_stream, 4),
+           "fifo_gib": round(fifo_bytes / 2**30, 2),
+           "merged_speedup": round(ms / fused_ms, 2) if fused_ms else None}
+    del g, ug
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_c3(steps, warmup):

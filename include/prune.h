@@ -96,7 +96,13 @@ enum { PRUNE_PORT_PARAM = 1u };
  *  SELECT      dynamic actor y: DRP inputs, one SRP output = sum of active
  *              inputs (the active input for one-hot control values).
  *  PASSTHROUGH static copy actor.
- *  SINK        one input port. */
+ *  SINK        one input port.
+ *  POLY        dynamic actor x of the unfused DPD graph (Sec. VII-A, Fig. 8):
+ *              a SWITCH whose k-th output port (creation order, k = 0..)
+ *              carries the basis u_{k+1} = |x|^k x of the window (halo
+ *              included), so output k feeds the FIR of branch k+1.
+ * Limits: at most PRUNE_MAX_PORTS ports per actor, PRUNE_MAX_IN data
+ * inputs, PRUNE_MAX_IO output FIFO accesses per firing. */
 enum {
   PRUNE_SOURCE = 0,
   PRUNE_CONFIG = 1,
@@ -104,8 +110,10 @@ enum {
   PRUNE_SWITCH = 3,
   PRUNE_SELECT = 4,
   PRUNE_PASSTHROUGH = 5,
-  PRUNE_SINK = 6
+  PRUNE_SINK = 6,
+  PRUNE_POLY = 7
 };
+enum { PRUNE_MAX_PORTS = 14, PRUNE_MAX_IN = 10, PRUNE_MAX_IO = 12 };
 
 /* Execution modes of prune_graph_fire. */
 enum {

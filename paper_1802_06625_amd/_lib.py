@@ -22,7 +22,8 @@ AN_LINKED, AN_DPGS, AN_DCS, AN_DC_ACTORS, AN_ACTOR_DC, AN_BETA, AN_VIOLATIONS = 
 IN, OUT = 0, 1
 SRP, DRP, CPORT = 0, 1, 2
 PORT_PARAM = 1
-SOURCE, CONFIG, FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK = range(7)
+SOURCE, CONFIG, FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK, POLY = range(8)
+MAX_PORTS, MAX_IN, MAX_IO = 14, 10, 12
 PER_FIRING, BATCHED, BATCHED_GRAPH = 0, 1, 2
 CONFIG_PREFIX, CONFIG_ROUTE = 0, 1
 MAX_BANKS, MAX_BRANCHES, MAX_L = 4, 32, 64

@@ -350,64 +350,35 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
       }
       if (tid == 0) { fb->branch_firings[dd] += fi; fb->branch_tokens[dd] += tk; }
     }
-  } else if (kind == PRUNE_SWITCH || kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH ||
-             kind == PRUNE_SOURCE || kind == PRUNE_SINK) {
+  } else if (kind == PRUNE_SWITCH || kind == PRUNE_POLY || kind == PRUNE_SELECT ||
+             kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK) {
+    // Items are counted first, then written in place at their scanned
+    // offsets (a per-lane array of items, indexed by slot, would live in
+    // scratch).
     CopyItem *CI = c.copy_items;
     for (uint32_t base = 0; base < B; base += nt) {
       const uint32_t i = base + tid;
+      const bool fired = i < B && R[i].fired;
       uint32_t nitems = 0;
-      CopyItem it[kMaxIO];
-      if (i < B && R[i].fired) {
-        if (kind == PRUNE_SWITCH) {
-          const float2 *hp = resolve_halo(c, a, i);
-          for (uint32_t k = 0; k < out_slot; ++k) {
-            if (!R[i].out[k].ptr) continue;
-            const PortDev &p = c.ports[A.port[R[i].out_port[k]]];
-            CopyItem &ci = it[nitems++];
-            ci.n_src = 1; ci.src[0] = (const float2 *)R[i].in[0].ptr;
-            for (int s = 1; s < kMaxIn; ++s) ci.src[s] = nullptr;
-            ci.dst = (float2 *)R[i].out[k].ptr;
-            ci.halo = hp + (A.hist_len - p.halo); ci.halo_count = p.halo;
-            ci.count = R[i].in[0].count;
-          }
+      if (fired) {
+        if (kind == PRUNE_SWITCH || kind == PRUNE_POLY) {
+          for (uint32_t k = 0; k < out_slot; ++k) nitems += R[i].out[k].ptr ? 1u : 0u;
         } else if (kind == PRUNE_SOURCE) {
-          if (R[i].in[0].ptr) {
-            for (uint32_t k = 0; k < out_slot; ++k) {
-              CopyItem &ci = it[nitems++];
-              ci.n_src = 1; ci.src[0] = (const float2 *)R[i].in[0].ptr;
-              for (int s = 1; s < kMaxIn; ++s) ci.src[s] = nullptr;
-              ci.dst = (float2 *)R[i].out[k].ptr; ci.halo = nullptr; ci.halo_count = 0;
-              ci.count = R[i].out[k].count;
-            }
-          }
+          nitems = R[i].in[0].ptr ? out_slot : 0u;
         } else if (kind == PRUNE_SINK) {
-          if (A.sink_out) {
-            CopyItem &ci = it[nitems++];
-            ci.n_src = 1; ci.src[0] = (const float2 *)R[i].in[0].ptr;
-            for (int s = 1; s < kMaxIn; ++s) ci.src[s] = nullptr;
-            ci.dst = nullptr;   // filled below with the running offset
-            ci.halo = nullptr; ci.halo_count = 0; ci.count = R[i].in[0].count;
-          }
+          nitems = A.sink_out ? 1u : 0u;
         } else {
-          // SELECT sums its active inputs; PASSTHROUGH copies its input.
-          for (uint32_t k = 0; k < out_slot; ++k) {
-            CopyItem &ci = it[nitems++];
-            ci.n_src = 0;
-            for (uint32_t s = 0; s < (uint32_t)kMaxIn; ++s)
-              if (R[i].in[s].ptr) ci.src[ci.n_src++] = (const float2 *)R[i].in[s].ptr;
-            for (uint32_t s = ci.n_src; s < (uint32_t)kMaxIn; ++s) ci.src[s] = nullptr;
-            ci.dst = (float2 *)R[i].out[k].ptr; ci.halo = nullptr; ci.halo_count = 0;
-            ci.count = R[i].out[k].count;
-          }
+          nitems = out_slot;
         }
       }
       // sink output offsets: running token offset over firings
-      uint32_t sink_tok = (kind == PRUNE_SINK && nitems) ? it[0].count : 0u;
+      const uint32_t sink_tok = (kind == PRUNE_SINK && nitems) ? R[i].in[0].count : 0u;
       uint32_t tot_tok;
       const uint32_t pre_tok = block_excl_scan(sink_tok, &tot_tok, sm32);
+      float2 *sink_dst = nullptr;
       if (kind == PRUNE_SINK && nitems) {
         const uint64_t off = A.sink_pos + pre_tok;
-        if (off + sink_tok <= A.sink_cap) it[0].dst = A.sink_out + off;
+        if (off + sink_tok <= A.sink_cap) sink_dst = A.sink_out + off;
         else { nitems = 0; atomicOr(c.err, kErrCount); }
       }
       uint32_t tot;
@@ -416,7 +387,46 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
       if (tid == 0) s_cres = atomicAdd(c.copy_count + c.level_of[a], tot);
       __syncthreads();
       const uint32_t off = c.copy_item_off[c.level_of[a]] + s_cres + pre;
-      for (uint32_t k = 0; k < nitems; ++k) CI[off + k] = it[k];
+      uint32_t w = 0;
+      auto item = [&](const float2 *src, float2 *dst, uint32_t count) -> CopyItem & {
+        CopyItem &ci = CI[off + w++];
+        ci.n_src = src ? 1u : 0u;
+        ci.src[0] = src;
+        for (int q = 1; q < kMaxIn; ++q) ci.src[q] = nullptr;
+        ci.dst = dst;
+        ci.halo = nullptr;
+        ci.halo_count = 0;
+        ci.count = count;
+        ci.pad = 0;
+        return ci;
+      };
+      if (nitems) {
+        if (kind == PRUNE_SWITCH || kind == PRUNE_POLY) {
+          const float2 *hp = resolve_halo(c, a, i);
+          for (uint32_t k = 0; k < out_slot; ++k) {
+            if (!R[i].out[k].ptr) continue;
+            const PortDev &p = c.ports[A.port[R[i].out_port[k]]];
+            CopyItem &ci = item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[k].ptr, R[i].in[0].count);
+            ci.halo = hp + (A.hist_len - p.halo);
+            ci.halo_count = p.halo;
+            ci.pad = p.power;
+          }
+        } else if (kind == PRUNE_SOURCE) {
+          for (uint32_t k = 0; k < out_slot; ++k)
+            item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[k].ptr, R[i].out[k].count);
+        } else if (kind == PRUNE_SINK) {
+          item((const float2 *)R[i].in[0].ptr, sink_dst, R[i].in[0].count);
+        } else {
+          // SELECT sums its active inputs; PASSTHROUGH copies its input.
+          for (uint32_t k = 0; k < out_slot; ++k) {
+            CopyItem &ci = item(nullptr, (float2 *)R[i].out[k].ptr, R[i].out[k].count);
+            uint32_t ns = 0;
+            for (int q = 0; q < kMaxIn; ++q)
+              if (R[i].in[q].ptr) ci.src[ns++] = (const float2 *)R[i].in[q].ptr;
+            ci.n_src = ns;
+          }
+        }
+      }
       if (tid == 0 && kind == PRUNE_SINK) A.sink_pos += tot_tok;
       __syncthreads();
     }
@@ -444,30 +454,45 @@ __global__ __launch_bounds__(1024) void k_control(CtrlArgs c) {
 // the level, y over chunks of kCopyChunk samples.
 constexpr uint32_t kCopyChunk = 4096;
 
+// Items with a nonzero power (POLY outputs) store |v|^power * v.  The item
+// is staged in LDS so that its source list is indexed there rather than in
+// per-lane scratch.
 __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items,
                                               const uint32_t *__restrict__ n_items) {
+  __shared__ CopyItem s_ci;
   const uint32_t n = *n_items;
   for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
-  const CopyItem ci = items[it];
-  const uint32_t total = ci.halo_count + ci.count;
-  const uint32_t lo = blockIdx.y * kCopyChunk;
-  if (lo >= total) continue;
-  const uint32_t hi = min(total, lo + kCopyChunk);
-  for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-    float2 v;
-    if (k < ci.halo_count) {
-      v = ci.halo[k];
-    } else {
-      const uint32_t s = k - ci.halo_count;
-      v = make_float2(0.f, 0.f);
-      for (uint32_t q = 0; q < ci.n_src; ++q) {
-        const float2 u = ci.src[q][s];
-        v.x += u.x;
-        v.y += u.y;
+    __syncthreads();
+    if (threadIdx.x == 0) s_ci = items[it];
+    __syncthreads();
+    const uint32_t halo_count = s_ci.halo_count, n_src = s_ci.n_src, power = s_ci.pad;
+    const uint32_t total = halo_count + s_ci.count;
+    const uint32_t lo = blockIdx.y * kCopyChunk;
+    if (lo >= total) continue;
+    const uint32_t hi = min(total, lo + kCopyChunk);
+    float2 *dst = s_ci.dst;
+    for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+      float2 v;
+      if (k < halo_count) {
+        v = s_ci.halo[k];
+      } else {
+        const uint32_t s = k - halo_count;
+        v = make_float2(0.f, 0.f);
+        for (uint32_t q = 0; q < n_src; ++q) {
+          const float2 u = s_ci.src[q][s];
+          v.x += u.x;
+          v.y += u.y;
+        }
       }
+      if (power) {
+        const float r = sqrtf(v.x * v.x + v.y * v.y);
+        float m = r;
+        for (uint32_t e = 1; e < power; ++e) m *= r;
+        v.x *= m;
+        v.y *= m;
+      }
+      dst[k] = v;
     }
-    ci.dst[k] = v;
-  }
   }
 }
 
@@ -650,7 +675,7 @@ __global__ __launch_bounds__(256) void k_batch_decode(CtrlArgs c, BatchArgs b) {
       if (fb) {
         const uint32_t n = fb->windowed ? in0 - (fb->Lmax - 1) : in0;
         aux = in0 ? (n + c.tile - 1) / c.tile : 0;
-      } else if (kind == PRUNE_SWITCH) {
+      } else if (kind == PRUNE_SWITCH || kind == PRUNE_POLY) {
         aux = n_act_out;
       } else if (kind == PRUNE_SOURCE) {
         aux = src_ptr ? n_out : 0;
@@ -836,7 +861,7 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
   }
 
   if (task == 1) {
-    if (!(kind == PRUNE_FILTERBANK || kind == PRUNE_SWITCH || kind == PRUNE_SELECT ||
+    if (!(kind == PRUNE_FILTERBANK || kind == PRUNE_SWITCH || kind == PRUNE_POLY || kind == PRUNE_SELECT ||
           kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK))
       return;
     const uint32_t lev = c.level_of[a];
@@ -951,7 +976,9 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
     const ActorDev &A = c.actors[a];
     const uint32_t kind = A.kind;
     const size_t ab = (size_t)a * Bc, o = ab + i;
-    FiringRec r;
+    // the firing record is written in place: a local copy indexed by access
+    // slot would live in per-lane scratch
+    FiringRec &r = c.recs[o];
     r.fired = b.s_fired[o];
     const uint32_t batch_fired = b.s_firing[ab + last] + b.s_fired[ab + last];
     r.firing = (uint32_t)(A.firings - batch_fired + b.s_firing[o]);
@@ -1000,7 +1027,6 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
                  (uint32_t)fifo_read_slot(f.r, f.Q, f.C, idx), 1u);
       trace_push(c, 1, a, 0u, r.firing, r.mask, r.rate, r.bitmap);
     }
-    c.recs[o] = r;
     if (!r.fired) return;
 
     if (kind == PRUNE_CONFIG) {
@@ -1012,7 +1038,8 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
     } else if (kind == PRUNE_FILTERBANK) {
       const FbParamsDev &fb = c.fbs[A.fb];
       const uint32_t H = fb.Lmax - 1;
-      FbFrameDesc d;
+      const uint32_t di = c.desc_off[a] + i;
+      FbFrameDesc &d = c.fb_desc[di];   // in place (its output list is indexed)
       const char *xin = r.in[0].ptr;
       const uint32_t cin = r.in[0].count;
       d.n = cin ? (fb.windowed ? cin - H : cin) : 0;
@@ -1026,8 +1053,6 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
       d.mask = r.bitmap;
       d.n_banks = fb.n_banks; d.Kmax = fb.Kmax; d.Lmax = fb.Lmax; d.route = 0;
       for (int q = 0; q < PRUNE_MAX_BANKS; ++q) d.L[q] = fb.L[q];
-      const uint32_t di = c.desc_off[a] + i;
-      c.fb_desc[di] = d;
       const uint32_t tiles = b.s_aux[o], base = b.s_auxoff[o];
       for (uint32_t t = 0; t < tiles; ++t) {
         WorkItem w;
@@ -1036,49 +1061,54 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
         c.fb_items[base + t] = w;
       }
     } else {
-      uint32_t base = b.s_auxoff[o], n = 0;
-      CopyItem ci;
-      for (int s = 0; s < kMaxIn; ++s) ci.src[s] = nullptr;
-      ci.halo = nullptr; ci.halo_count = 0; ci.pad = 0;
-      if (kind == PRUNE_SWITCH) {
+      // copy items are written in place (their source list is indexed)
+      const uint32_t base = b.s_auxoff[o];
+      uint32_t n = 0;
+      auto item = [&](const float2 *src, float2 *dst, uint32_t count) -> CopyItem & {
+        CopyItem &ci = c.copy_items[base + n++];
+        ci.n_src = src ? 1u : 0u;
+        ci.src[0] = src;
+        for (int q = 1; q < kMaxIn; ++q) ci.src[q] = nullptr;
+        ci.dst = dst;
+        ci.halo = nullptr;
+        ci.halo_count = 0;
+        ci.count = count;
+        ci.pad = 0;
+        return ci;
+      };
+      if (kind == PRUNE_SWITCH || kind == PRUNE_POLY) {
         const float2 *hp = batch_halo(c, b, a, in_acc, i);
         for (uint32_t k = 0; k < n_out; ++k) {
           if (!r.out[k].ptr) continue;
           const PortDev &p = c.ports[r.out_port[k]];
-          ci.n_src = 1; ci.src[0] = (const float2 *)r.in[0].ptr;
-          ci.dst = (float2 *)r.out[k].ptr;
-          ci.halo = hp + (A.hist_len - p.halo); ci.halo_count = p.halo;
-          ci.count = r.in[0].count;
-          c.copy_items[base + n++] = ci;
+          CopyItem &ci = item((const float2 *)r.in[0].ptr, (float2 *)r.out[k].ptr, r.in[0].count);
+          ci.halo = hp + (A.hist_len - p.halo);
+          ci.halo_count = p.halo;
+          ci.pad = p.power;
         }
       } else if (kind == PRUNE_SOURCE) {
         const SrcIn sin = ((const SrcIn *)A.queue)[(b.s_qbase[a] + i) % A.q_cap];
         if (sin.ptr)
-          for (uint32_t k = 0; k < n_out; ++k) {
-            ci.n_src = 1; ci.src[0] = (const float2 *)sin.ptr;
-            ci.dst = (float2 *)r.out[k].ptr; ci.count = r.out[k].count;
-            c.copy_items[base + n++] = ci;
-          }
+          for (uint32_t k = 0; k < n_out; ++k)
+            item((const float2 *)sin.ptr, (float2 *)r.out[k].ptr, r.out[k].count);
       } else if (kind == PRUNE_SINK) {
         if (A.sink_out) {
           const uint64_t off = b.s_sink[a] + b.s_aux2[o];
-          ci.n_src = 1; ci.src[0] = (const float2 *)r.in[0].ptr; ci.count = r.in[0].count;
-          if (off + ci.count <= A.sink_cap) {
-            ci.dst = A.sink_out + off;
+          const uint32_t cnt = r.in[0].count;
+          if (off + cnt <= A.sink_cap) {
+            item((const float2 *)r.in[0].ptr, A.sink_out + off, cnt);
           } else {
-            ci.dst = nullptr; ci.count = 0; ci.n_src = 0;
+            item(nullptr, A.sink_out, 0);
             atomicOr(c.err, kErrCount);
           }
-          if (ci.dst) c.copy_items[base + n++] = ci;
-          else { ci.dst = A.sink_out; c.copy_items[base + n++] = ci; }
         }
       } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
         for (uint32_t k = 0; k < n_out; ++k) {
-          ci.n_src = 0;
-          for (int s = 0; s < kMaxIn; ++s)
-            if (r.in[s].ptr) ci.src[ci.n_src++] = (const float2 *)r.in[s].ptr;
-          ci.dst = (float2 *)r.out[k].ptr; ci.count = r.out[k].count;
-          c.copy_items[base + n++] = ci;
+          CopyItem &ci = item(nullptr, (float2 *)r.out[k].ptr, r.out[k].count);
+          uint32_t ns = 0;
+          for (int q = 0; q < kMaxIn; ++q)
+            if (r.in[q].ptr) ci.src[ns++] = (const float2 *)r.in[q].ptr;
+          ci.n_src = ns;
         }
       }
     }

@@ -12,9 +12,9 @@
 
 namespace prune {
 
-constexpr int kMaxPorts = 8;          // ports per actor, control port included
+constexpr int kMaxPorts = PRUNE_MAX_PORTS;   // ports per actor, control port included
 constexpr int kMaxFanout = 4;         // FIFOs per output port (broadcast)
-constexpr int kMaxIO = 8;             // data FIFO accesses per firing
+constexpr int kMaxIO = PRUNE_MAX_IO;         // data FIFO accesses per firing
 constexpr uint32_t kNone = 0xffffffffu;
 
 // Device error word bits (reported by prune_graph_sync).
@@ -103,6 +103,7 @@ struct PortDev {
   uint32_t actor, dir, kind, atr;
   uint32_t param, halo, element;   // element: control-table entry of a DRP
   uint32_t n_fifos;
+  uint32_t power;                  // POLY output k: basis |x|^k x (0 elsewhere)
   uint32_t fifo[kMaxFanout];
 };
 
@@ -137,7 +138,7 @@ struct IoRec {
   uint32_t count, fifo;
 };
 
-constexpr int kMaxIn = 4;   // data inputs per actor
+constexpr int kMaxIn = PRUNE_MAX_IN;   // data inputs per actor
 
 struct FiringRec {
   uint32_t fired, firing, mask, rate;

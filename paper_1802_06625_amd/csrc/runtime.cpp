@@ -267,7 +267,7 @@ prune_status validate_actor(prune_graph *g, uint32_t aid) {
     }
     return PRUNE_OK;
   }
-  const bool dyn_kind = a.kind == PRUNE_SWITCH || a.kind == PRUNE_SELECT;
+  const bool dyn_kind = a.kind == PRUNE_SWITCH || a.kind == PRUNE_POLY || a.kind == PRUNE_SELECT;
   const bool dynamic = dyn_kind || (a.kind == PRUNE_FILTERBANK && !cps.empty());
   if (!dynamic) {
     if (!cps.empty() || !in_drp.empty() || !out_drp.empty())
@@ -323,6 +323,7 @@ prune_status validate_actor(prune_graph *g, uint32_t aid) {
       break;
     }
     case PRUNE_SWITCH:
+    case PRUNE_POLY:
       if (din.size() != 1 || din[0]->kind != PRUNE_SRP || outs.empty())
         return err(PRUNE_E_ARG, "one SRP input, DRP outputs");
       for (HPort *p : outs) {
@@ -335,7 +336,7 @@ prune_status validate_actor(prune_graph *g, uint32_t aid) {
     case PRUNE_SELECT:
       if (outs.size() != 1 || outs[0]->kind != PRUNE_SRP || in_drp.empty() || in_drp.size() != din.size())
         return err(PRUNE_E_ARG, "DRP inputs, one SRP output");
-      if (din.size() > (size_t)kMaxIn) return fail(PRUNE_E_UNSUPPORTED, "more than 4 select inputs");
+      if (din.size() > (size_t)kMaxIn) return fail(PRUNE_E_UNSUPPORTED, "more than PRUNE_MAX_IN select inputs");
       for (HPort *p : din)
         if (p->atr != outs[0]->atr || (p->flags & PRUNE_PORT_PARAM) != (outs[0]->flags & PRUNE_PORT_PARAM) || p->halo)
           return err(PRUNE_E_RATE_MISMATCH, "input and output rates differ");
@@ -343,13 +344,13 @@ prune_status validate_actor(prune_graph *g, uint32_t aid) {
     default:
       return err(PRUNE_E_ARG, "unknown actor kind");
   }
-  if (a.ports.size() > (size_t)kMaxPorts) return fail(PRUNE_E_UNSUPPORTED, "more than 8 ports on an actor");
+  if (a.ports.size() > (size_t)kMaxPorts) return fail(PRUNE_E_UNSUPPORTED, "more than PRUNE_MAX_PORTS ports on an actor");
   size_t nio = 0;
   for (HPort *p : outs) {
     if (p->fifos.size() > (size_t)kMaxFanout) return fail(PRUNE_E_UNSUPPORTED, "more than 4 FIFOs on a port");
     nio += p->fifos.size();
   }
-  if (nio > (size_t)kMaxIO) return fail(PRUNE_E_UNSUPPORTED, "more than 8 output FIFO accesses");
+  if (nio > (size_t)kMaxIO) return fail(PRUNE_E_UNSUPPORTED, "more than PRUNE_MAX_IO output FIFO accesses");
   return PRUNE_OK;
 }
 
@@ -373,6 +374,13 @@ prune_status build_device(prune_graph *g) {
     }
     d.n_fifos = (uint32_t)P.fifos.size();
     for (size_t k = 0; k < P.fifos.size(); ++k) d.fifo[k] = P.fifos[k];
+    d.power = 0;
+    if (g->actors[P.actor].kind == PRUNE_POLY && P.dir == PRUNE_OUT) {
+      for (uint32_t q : g->actors[P.actor].ports) {
+        if (q == p) break;
+        if (g->ports[q].dir == PRUNE_OUT) ++d.power;
+      }
+    }
     P.dev = (uint32_t)g->h_ports.size();
     g->h_ports.push_back(d);
   }
@@ -455,7 +463,7 @@ prune_status build_device(prune_graph *g) {
     d.fb = A.fb_index;
     d.fixed_mask = A.fb.fixed_mask;
     if (A.kind == PRUNE_FILTERBANK && !A.fb.windowed) A.hist_len = fb_lmax(A.fb) - 1;
-    if (A.kind == PRUNE_SWITCH) {
+    if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_POLY) {
       for (uint32_t p : A.ports)
         if (g->ports[p].dir == PRUNE_OUT) A.hist_len = std::max(A.hist_len, g->ports[p].halo);
     }
@@ -564,7 +572,7 @@ uint32_t out_accesses(const prune_graph *g, const HActor &a) {
 }
 
 bool is_copy_kind(uint32_t k) {
-  return k == PRUNE_SWITCH || k == PRUNE_SELECT || k == PRUNE_PASSTHROUGH || k == PRUNE_SOURCE ||
+  return k == PRUNE_SWITCH || k == PRUNE_POLY || k == PRUNE_SELECT || k == PRUNE_PASSTHROUGH || k == PRUNE_SOURCE ||
          k == PRUNE_SINK;
 }
 
@@ -920,7 +928,8 @@ void launch_masks(prune_graph *g, uint32_t B, uint64_t *copy_mask, uint64_t *gat
   *gather_mask = 0;
   for (auto &A : g->actors) {
     const uint64_t bit = 1ull << std::min<uint32_t>(A.level, 63);
-    if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_SELECT || A.kind == PRUNE_PASSTHROUGH) *copy_mask |= bit;
+    if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_POLY || A.kind == PRUNE_SELECT || A.kind == PRUNE_PASSTHROUGH)
+      *copy_mask |= bit;
     if (A.kind == PRUNE_SINK && A.sink_out) *copy_mask |= bit;
     if (A.kind == PRUNE_SOURCE) {
       for (uint32_t k = 0; k < B && k < A.src_q.size(); ++k)
@@ -1090,7 +1099,7 @@ prune_status prune_graph_destroy(prune_graph_t g) {
 prune_status prune_actor_create(prune_graph_t g, int kind, const void *params, size_t bytes,
                                 prune_id *actor) {
   TRY(check_graph(g, false));
-  if (!actor || kind < PRUNE_SOURCE || kind > PRUNE_SINK) return fail(PRUNE_E_ARG, "bad actor kind");
+  if (!actor || kind < PRUNE_SOURCE || kind > PRUNE_POLY) return fail(PRUNE_E_ARG, "bad actor kind");
   HActor a;
   a.kind = (uint32_t)kind;
   if (kind == PRUNE_CONFIG) {

@@ -252,6 +252,56 @@ class PlainGraph:
         self.fifo_out = g.alloc_fifo(self.f_out)
 
 
+class UnfusedGraph:
+    """The DPD graph before actor merging (Sec. VII-A, Fig. 8): SOURCE -> POLY
+    (dynamic x; output b carries |x|^b x over the window of L-1 past samples
+    and the frame) -> FIR_b (a static windowed filter bank with one branch,
+    taps of branch b) -> SELECT (dynamic y, the add: sum of its active
+    inputs) -> SINK; CONFIG (prefix mode) broadcasts one control value to
+    POLY and SELECT, branch b <- element b+1.  One bank, Kmax <= PRUNE_MAX_IN."""
+
+    def __init__(self, Kmax, L_, atr, C_, device=0):
+        g = self.g = Graph(device)
+        H = L_ - 1
+        self.src = g.actor(L.SOURCE)
+        self.cfg = g.config(L.CONFIG_PREFIX, Kmax, Kmax)
+        self.poly = g.actor(L.POLY)
+        self.firs = [g.filterbank(1, [L_], windowed=True, fixed_mask=1) for _ in range(Kmax)]
+        self.add = g.actor(L.SELECT)
+        self.snk = g.actor(L.SINK)
+        p_src = g.port(self.src, L.OUT, L.SRP, atr)
+        p_ctl = g.port(self.cfg, L.OUT, L.SRP, 1)
+        p_pc = g.port(self.poly, L.IN, L.CPORT, 1)
+        p_pi = g.port(self.poly, L.IN, L.SRP, atr)
+        p_po = [g.port(self.poly, L.OUT, L.DRP, atr + H, halo=H) for _ in range(Kmax)]
+        p_fi = [g.port(f, L.IN, L.SRP, atr + H, halo=H) for f in self.firs]
+        p_fo = [g.port(f, L.OUT, L.SRP, atr) for f in self.firs]
+        p_ac = g.port(self.add, L.IN, L.CPORT, 1)
+        p_ai = [g.port(self.add, L.IN, L.DRP, atr) for _ in range(Kmax)]
+        p_ao = g.port(self.add, L.OUT, L.SRP, atr)
+        p_snk = g.port(self.snk, L.IN, L.SRP, atr)
+        self.f_in = g.connect(p_src, p_pi, atr)
+        g.connect(p_ctl, p_pc, 1)
+        g.connect(p_ctl, p_ac, 1)
+        self.f_win, self.f_br = [], []
+        for b in range(Kmax):
+            self.f_win.append(g.connect(p_po[b], p_fi[b], atr + H))
+            self.f_br.append(g.connect(p_fo[b], p_ai[b], atr))
+            g.control(p_ctl, p_po[b], b + 1)
+            g.control(p_ctl, p_ai[b], b + 1)
+        self.f_out = g.connect(p_ao, p_snk, atr)
+        g.finalize(C_, check_rules=True)
+        self.atr = atr
+        self.fifo_in = g.alloc_fifo(self.f_in)
+        self.fifo_out = g.alloc_fifo(self.f_out)
+        self.storage = [g.alloc_fifo(f) for f in self.f_win + self.f_br]
+
+    def set_taps(self, taps):
+        """taps: [Kmax, L] complex (branch b's FIR)."""
+        for b, f in enumerate(self.firs):
+            self.g.set_taps(f, taps[b:b + 1].reshape(1, 1, -1).contiguous())
+
+
 class RoutedGraph:
     """Per stream: SOURCE -> SWITCH -> {FILTERBANK (static, windowed),
     PASSTHROUGH} -> SELECT -> SINK, with one CONFIG (route mode)
