@@ -120,7 +120,8 @@ def main():
               "c4": lambda: bench_direct("C4", args.steps, args.warmup),
               "c5": lambda: bench_c5(args.steps, args.warmup),
               "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup),
-              "c2u": lambda: bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), None)}[args.only]
+              "c2u": lambda: bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), None),
+              "paper": lambda: bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5))}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     if args.copy_calib:
@@ -244,6 +245,8 @@ def main():
     if not args.only_c2:
         print("bench: unfused DPD graph", file=sys.stderr, flush=True)
         out["c2_unfused"] = bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), ms_step)
+        print("bench: the paper's DPD shape", file=sys.stderr, flush=True)
+        out["paper_dpd"] = bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5))
         print("bench: fwd+bwd (differentiation workload)", file=sys.stderr, flush=True)
         out["c4_fwd_bwd"] = bench_direct("C4", args.steps, args.warmup)
         print("bench: batched uneven frames", file=sys.stderr, flush=True)
@@ -413,6 +416,53 @@ def bench_c2_unfused(steps, warmup, fused_ms):
            "merged_speedup": round(ms / fused_ms, 2) if fused_ms else None}
     del g, ug
     torch.cuda.empty_cache()
+    return res
+
+
+# The paper's DPD throughput with PRUNE on its heterogeneous platforms
+# (complex-float Msamples/s, Table IV): context for the same graph shape.
+PAPER_DPD_MSAMPLES = {"AMD Radeon RX 460 (PCIe)": 106.0, "AMD Carrizo R7 iGPU": 39.5,
+                      "Intel i7-6700HQ OpenCL": 25.1}
+
+
+def bench_paper_dpd(steps, warmup):
+    """The shape of the paper's DPD run (1024 frames x 65536, K~U{2..10},
+    L=10, 2^26 samples) through the merged filter bank and through the
+    unfused graph of the paper (poly -> 10 FIR_b -> add)."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import PlainGraph, UnfusedGraph
+    wl = synth.make("P")
+    side = wl.side[0]
+    F, n = side.shape[0], int(side[0, 1])
+    x = torch.from_numpy(wl.x[0]).cuda()
+    taps = torch.from_numpy(wl.taps[0]).cuda()
+    del wl.x
+    res = {"workload": wl.spec.description, "samples": F * n}
+    for name in ("merged", "unfused"):
+        if name == "merged":
+            G = PlainGraph(wl.Kmax, wl.bank_L, n, F)
+            G.g.set_taps(G.fb, taps)
+        else:
+            G = UnfusedGraph(wl.Kmax, wl.bank_L[0], n, F)
+            G.set_taps(taps[0])
+        g = G.g
+        G.fifo_in.view(F, n).copy_(x.view(F, n))
+        for _ in range(2 * (steps + warmup) + 1):
+            g.source_push(G.src, None, side[:, 1])
+            g.config_push(G.cfg, side)
+        torch.cuda.synchronize()
+        g.fire(L.BATCHED_GRAPH, F)
+        ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
+        ms_stream = _time_events(lambda: g.fire(L.BATCHED, F), steps, warmup)
+        g.sync()
+        ms = min(ms_graph, ms_stream)
+        res[name] = {"msamples": round(F * n / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
+                     "mode": "batched_graph" if ms_graph <= ms_stream else "batched_stream"}
+        del g, G
+        torch.cuda.empty_cache()
+    res["paper_prune_heterogeneous_msamples"] = PAPER_DPD_MSAMPLES
     return res
 
 

@@ -130,7 +130,10 @@ enum {
 /* Configuration actor modes (how side-information becomes a control value). */
 enum {
   PRUNE_CONFIG_PREFIX = 0, /* mask = ((1 << K) - 1) << (bank * Kmax)        */
-  PRUNE_CONFIG_ROUTE = 1   /* mask = 1 << route (one-hot DC selection)     */
+  PRUNE_CONFIG_ROUTE = 1,  /* mask = 1 << route (one-hot DC selection)     */
+  PRUNE_CONFIG_MASK = 2    /* mask = (K & ((1 << Kmax) - 1)) << (bank * Kmax):
+                              K carries any set of the bank's branches
+                              (bit b-1 = branch b), not only a prefix      */
 };
 
 /* Control token (8 bytes): the control value v (bit e-1 = element e) and

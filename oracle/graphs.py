@@ -28,11 +28,11 @@ def _frames_of(wl, s):
     return [wl.x[s, off[f]:off[f + 1]] for f in range(wl.n_frames)]
 
 
-def build_plain(taps, bank_L, Kmax, atr, C, param=False):
+def build_plain(taps, bank_L, Kmax, atr, C, param=False, cfg_mode="prefix"):
     g = Graph()
     D = len(bank_L) * Kmax
     src = g.actor(SOURCE)
-    cfg = g.actor(CONFIG, mode="prefix", Kmax=Kmax, n_elements=D)
+    cfg = g.actor(CONFIG, mode=cfg_mode, Kmax=Kmax, n_elements=D)
     fb = g.actor(FILTERBANK, taps=np.asarray(taps), bank_L=list(bank_L), Kmax=Kmax)
     snk = g.actor(SINK)
     p_src = g.port(src, OUT, SRP, atr, param)
@@ -51,14 +51,15 @@ def build_plain(taps, bank_L, Kmax, atr, C, param=False):
     return g, ids
 
 
-def run_plain(wl, C=3, s=0, atr=None, param=None, policy="round_robin", rng=None):
+def run_plain(wl, C=3, s=0, atr=None, param=None, policy="round_robin", rng=None,
+              cfg_mode="prefix"):
     """Run the plain graph over stream s of a workload; returns (y, logs, g, ids)."""
     n = wl.side[s, :, 1]
     if param is None:
         param = bool(np.any(n != n[0]))
     if atr is None:
         atr = int(wl.spec.n_max) if param else int(n[0])
-    g, ids = build_plain(wl.taps[s], wl.bank_L, wl.Kmax, atr, C, param)
+    g, ids = build_plain(wl.taps[s], wl.bank_L, wl.Kmax, atr, C, param, cfg_mode)
     g.push(ids["src"], _frames_of(wl, s))
     g.push(ids["cfg"], wl.side[s])
     g.run(policy=policy, rng=rng)

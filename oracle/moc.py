@@ -445,8 +445,15 @@ class Graph:
     @staticmethod
     def config_token(params, side):
         K, n, bank, route = (int(v) for v in side)
-        if params.get("mode", "prefix") == "route":
+        mode = params.get("mode", "prefix")
+        if mode == "route":
             mask = 1 << route
+        elif mode == "mask":
+            # K carries any set of the bank's branches (bit b-1 = branch b)
+            Kmax = params["Kmax"]
+            if K >> Kmax:
+                raise PruneError(E_TOKEN, "branch set beyond the bank size")
+            mask = K << (bank * Kmax)
         else:
             Kmax = params["Kmax"]
             if K > Kmax:

@@ -25,7 +25,7 @@ PORT_PARAM = 1
 SOURCE, CONFIG, FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK, POLY = range(8)
 MAX_PORTS, MAX_IN, MAX_IO = 14, 10, 12
 PER_FIRING, BATCHED, BATCHED_GRAPH = 0, 1, 2
-CONFIG_PREFIX, CONFIG_ROUTE = 0, 1
+CONFIG_PREFIX, CONFIG_ROUTE, CONFIG_MASK = 0, 1, 2
 MAX_BANKS, MAX_BRANCHES, MAX_L = 4, 32, 64
 
 

@@ -80,6 +80,10 @@ __host__ __device__ inline prune_ctrl_token config_map(uint32_t mode, uint32_t K
   prune_ctrl_token t;
   if (mode == PRUNE_CONFIG_ROUTE) {
     t.mask = s.route < 32 ? (1u << s.route) : 0u;
+  } else if (mode == PRUNE_CONFIG_MASK) {
+    const uint32_t bank_bits = Kmax >= 32 ? 0xffffffffu : ((1u << Kmax) - 1u);
+    const uint32_t sh = s.bank * Kmax;
+    t.mask = sh < 32 ? ((s.K & bank_bits) << sh) : 0u;
   } else {
     uint32_t K = s.K > 31 ? 31 : s.K;
     uint32_t m = K ? ((K >= 32) ? 0xffffffffu : ((1u << K) - 1u)) : 0u;

@@ -1105,7 +1105,7 @@ prune_status prune_actor_create(prune_graph_t g, int kind, const void *params, s
   if (kind == PRUNE_CONFIG) {
     if (!params || bytes != sizeof(prune_config_params)) return fail(PRUNE_E_ARG, "config params expected");
     a.cfg = *(const prune_config_params *)params;
-    if (a.cfg.mode > PRUNE_CONFIG_ROUTE || a.cfg.n_elements > 32) return fail(PRUNE_E_ARG, "bad config params");
+    if (a.cfg.mode > PRUNE_CONFIG_MASK || a.cfg.n_elements > 32) return fail(PRUNE_E_ARG, "bad config params");
   } else if (kind == PRUNE_FILTERBANK) {
     if (!params || bytes != sizeof(prune_fb_params)) return fail(PRUNE_E_ARG, "filter-bank params expected");
     a.fb = *(const prune_fb_params *)params;
@@ -1555,7 +1555,7 @@ prune_status prune_rule_slots(uint32_t r, uint32_t Q, uint32_t C, uint32_t n, ui
 
 prune_status prune_rule_config_token(uint32_t mode, uint32_t Kmax, const prune_side_info *side,
                                      prune_ctrl_token *out) {
-  if (!side || !out || mode > PRUNE_CONFIG_ROUTE) return fail(PRUNE_E_ARG, "bad arguments");
+  if (!side || !out || mode > PRUNE_CONFIG_MASK) return fail(PRUNE_E_ARG, "bad arguments");
   *out = config_map(mode, Kmax, *side);
   return PRUNE_OK;
 }

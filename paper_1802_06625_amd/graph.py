@@ -227,12 +227,12 @@ class PlainGraph:
     """SOURCE -> FILTERBANK (merged DPG with control port) -> SINK; CONFIG
     (prefix mode) feeds the control port; branch d <- element d+1."""
 
-    def __init__(self, Kmax, bank_L, atr, C_, param=False, device=0):
+    def __init__(self, Kmax, bank_L, atr, C_, param=False, device=0, cfg_mode=L.CONFIG_PREFIX):
         g = self.g = Graph(device)
         D = len(bank_L) * Kmax
         fl = L.PORT_PARAM if param else 0
         self.src = g.actor(L.SOURCE)
-        self.cfg = g.config(L.CONFIG_PREFIX, Kmax, D)
+        self.cfg = g.config(cfg_mode, Kmax, D)
         self.fb = g.filterbank(Kmax, bank_L)
         self.snk = g.actor(L.SINK)
         p_src = g.port(self.src, L.OUT, L.SRP, atr, flags=fl)

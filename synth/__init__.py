@@ -46,6 +46,7 @@ class Spec:
     bank_L: tuple             # taps per branch for each bank
     pass_prob: float          # probability a frame is routed to passthrough
     description: str
+    K_min: int = 1            # K ~ U{K_min..Kmax} when K_fixed == 0
 
 
 SPECS = {
@@ -64,6 +65,11 @@ SPECS = {
     # Wide multi-stream graph with passthrough routing.
     "C5": Spec("C5", 64, 16, 32768, 0, 0, 7, 7, (64,), 0.3,
                "64 streams x 16 frames x 32768, K=7, L=64, ~30% passthrough"),
+    # The shape of the paper's DPD run (Sec. VII-A/C): ten 10-tap branches,
+    # a reconfiguration every 65536 samples with 2..10 active branches (the
+    # distribution is not given: uniform here), 2^26 samples in all.
+    "P": Spec("P", 1, 1024, 65536, 0, 0, 10, 0, (10,), 0.0,
+              "1024 frames x 65536 complex64, K~U{2..10}, L=10 (the paper's DPD shape)", K_min=2),
 }
 
 
@@ -111,7 +117,7 @@ def _draw_side(spec: Spec, g: np.random.Generator, S: int, F: int,
     lo, hi = math.log(spec.n_min or 1), math.log(spec.n_max or 1)
     for s in range(S):
         for f in range(F):
-            K = spec.K_fixed if spec.K_fixed else int(g.integers(1, spec.Kmax + 1))
+            K = spec.K_fixed if spec.K_fixed else int(g.integers(spec.K_min, spec.Kmax + 1))
             if spec.frame_len == 0 and frame_len == 0:
                 n = int(np.rint(math.exp(g.uniform(lo, hi))))
                 n = min(max(n, spec.n_min), spec.n_max)
@@ -190,6 +196,7 @@ def scaled(name: str, seed: int = 0, **kw) -> Workload:
         "C3": dict(n_frames=24, n_max=6000),
         "C4": dict(n_frames=6, frame_len=1500),
         "C5": dict(n_streams=3, n_frames=5, frame_len=1200),
+        "P": dict(n_frames=6, frame_len=2500),
     }[name]
     small.update(kw)
     return make(name, seed=seed, **small)

@@ -22,13 +22,13 @@ def announce(msg):
 
 
 def run_plain_device(wl, C, mode, s=0, atr=None, param=None, inplace=False, trace=True,
-                     batches=None):
+                     batches=None, cfg_mode=L.CONFIG_PREFIX):
     n = wl.side[s, :, 1].astype(np.int64)
     if param is None:
         param = bool(np.any(n != n[0]))
     if atr is None:
         atr = int(wl.spec.n_max) if param else int(n[0])
-    pg = PlainGraph(wl.Kmax, wl.bank_L, atr, C, param)
+    pg = PlainGraph(wl.Kmax, wl.bank_L, atr, C, param, cfg_mode=cfg_mode)
     g = pg.g
     g.set_taps(pg.fb, torch.from_numpy(wl.taps[s]).cuda())
     total = int(n.sum())

@@ -53,14 +53,14 @@ def test_rules_match_oracle(r, Q, C):
 def test_config_token_matches_oracle():
     import ctypes
     rng = np.random.default_rng(0)
-    for _ in range(500):
-        mode = int(rng.integers(0, 2))
+    for _ in range(900):
+        mode = int(rng.integers(0, 3))
         Kmax = int(rng.integers(1, 11))
-        side = L.SideInfo(int(rng.integers(0, Kmax + 1)), int(rng.integers(1, 70000)),
-                          int(rng.integers(0, 3)), int(rng.integers(0, 5)))
+        K = int(rng.integers(0, 1 << Kmax)) if mode == L.CONFIG_MASK else int(rng.integers(0, Kmax + 1))
+        side = L.SideInfo(K, int(rng.integers(1, 70000)), int(rng.integers(0, 3)), int(rng.integers(0, 5)))
         tok = L.CtrlToken()
         assert L.lib().prune_rule_config_token(mode, Kmax, ctypes.byref(side), ctypes.byref(tok)) == 0
-        mask, rate = moc.Graph.config_token(dict(mode="route" if mode else "prefix", Kmax=Kmax),
+        mask, rate = moc.Graph.config_token(dict(mode=("prefix", "route", "mask")[mode], Kmax=Kmax),
                                             (side.K, side.n, side.bank, side.route))
         assert (tok.mask, tok.rate) == (mask, rate)
 

@@ -221,13 +221,13 @@ def _run_unfused_device(wl, C, mode):
 
 
 @pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH])
-@pytest.mark.parametrize("name", ["C1", "C2"])
+@pytest.mark.parametrize("name", ["C1", "C2", "P"])
 def test_unfused_dpd_graph(mode, name):
     """The DPD graph before merging (poly -> FIR_b -> add): per-branch window
     and output FIFOs logged bit-exactly against the oracle's unfused graph,
     output within 2e-5 of it and of the merged filter bank."""
     announce(f"unfused DPD graph {name} mode={mode}")
-    wl = synth.make("C1") if name == "C1" else synth.scaled("C2")
+    wl = synth.make("C1") if name == "C1" else synth.scaled(name)
     C = 8
     y_ref, logs_ref, ids = _run_unfused_oracle(wl, C)
     dev = _run_unfused_device(wl, C, mode)
@@ -238,3 +238,21 @@ def test_unfused_dpd_graph(mode, name):
         assert dev["g"].actor_firings(a) == logs_ref["actors"][a]["firings"], a
     fused = run_plain_device(wl, C, mode, trace=False)
     assert rel_l2(dev["y"], fused["y"]) <= TOL
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED_GRAPH])
+def test_plain_arbitrary_branch_sets(mode):
+    """Configuration mode "mask": non-prefix branch sets per frame, logs
+    bit-exact and outputs within 2e-5 of the oracle."""
+    announce(f"plain C2-scaled arbitrary branch sets mode={mode}")
+    wl = synth.scaled("C2")
+    rng = np.random.default_rng(11)
+    wl.side[0, :, 0] = rng.integers(0, 1 << wl.Kmax, size=wl.n_frames)
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=8, cfg_mode="mask")
+    dev = run_plain_device(wl, 8, mode, cfg_mode=L.CONFIG_MASK)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+    compare_stats(dev["g"], logs_ref)
+    bf, bt = dev["g"].branch_stats(dev["pg"].fb, wl.Kmax)
+    assert bf == logs_ref["actors"][ids["fb"]]["branch_firings"]
+    assert bt == logs_ref["actors"][ids["fb"]]["branch_tokens"]

@@ -422,3 +422,25 @@ def test_mask_zero_outputs_zeros():
     y, logs, g, ids = graphs.run_plain(wl, C=3)
     assert np.all(y[:32] == 0) and np.all(y[64:96] == 0)
     assert np.any(y[32:64] != 0)
+
+
+# ---------------------------------------------------------------- arbitrary branch sets
+def test_mask_mode_branch_sets_add_up():
+    """Configuration mode "mask": any set of branches, not only a prefix.
+    The filter bank is linear in its branch set, so a frame's output under a
+    set equals the sum of its outputs under each single branch, and a prefix
+    set reproduces the prefix mode."""
+    wl = synth.make("C1", n_frames=6, frame_len=96)
+    rng = np.random.default_rng(3)
+    sets = [int(v) for v in rng.integers(1, 1 << wl.Kmax, size=wl.n_frames)]
+    def run(masks):
+        w = synth.make("C1", n_frames=6, frame_len=96)
+        w.side[0, :, 0] = masks
+        y, _, _, _ = graphs.run_plain(w, C=3, cfg_mode="mask")
+        return y
+    y = run(sets)
+    parts = sum(run([m & (1 << b) for m in sets]) for b in range(wl.Kmax))
+    np.testing.assert_allclose(y, parts, rtol=0, atol=1e-12)
+    pre = [(1 << k) - 1 for k in wl.side[0, :, 0]]
+    y_prefix, _, _, _ = graphs.run_plain(wl, C=3)
+    np.testing.assert_allclose(run(pre), y_prefix, rtol=0, atol=0)
