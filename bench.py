@@ -121,7 +121,8 @@ def main():
               "c5": lambda: bench_c5(args.steps, args.warmup),
               "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup),
               "c2u": lambda: bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), None),
-              "paper": lambda: bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5))}[args.only]
+              "paper": lambda: bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5)),
+              "host": lambda: bench_host_stream()}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     if args.copy_calib:
@@ -245,6 +246,8 @@ def main():
     if not args.only_c2:
         print("bench: unfused DPD graph", file=sys.stderr, flush=True)
         out["c2_unfused"] = bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), ms_step)
+        print("bench: host source and sink over PCIe", file=sys.stderr, flush=True)
+        out["c2_host_stream"] = bench_host_stream()
         print("bench: the paper's DPD shape", file=sys.stderr, flush=True)
         out["paper_dpd"] = bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5))
         print("bench: fwd+bwd (differentiation workload)", file=sys.stderr, flush=True)
@@ -463,6 +466,40 @@ def bench_paper_dpd(steps, warmup):
         del g, G
         torch.cuda.empty_cache()
     res["paper_prune_heterogeneous_msamples"] = PAPER_DPD_MSAMPLES
+    return res
+
+
+def bench_host_stream(batch=512):
+    """The headline workload with a host source and sink
+    (prune_graph_stream_host): frames from pinned host memory, outputs back
+    to pinned host memory, copies in both directions overlapped with the
+    firing.  PCIe-inclusive; the headline value keeps inputs in HBM."""
+    import torch
+    import synth
+    from paper_1802_06625_amd.graph import PlainGraph
+    wl = synth.make("C2")
+    side = wl.side[0]
+    F, n = side.shape[0], int(side[0, 1])
+    hin = torch.from_numpy(wl.x[0]).pin_memory()
+    del wl.x
+    hout = torch.empty(hin.shape, dtype=hin.dtype).pin_memory()
+    pg = PlainGraph(wl.Kmax, wl.bank_L, n, 2 * batch)
+    g = pg.g
+    g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    # one warm pass over the first batches, then the timed pass over all frames
+    g.stream_host(pg.src, pg.cfg, pg.snk, hin[:4 * batch * n], side[:4 * batch], hout[:4 * batch * n], batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.stream_host(pg.src, pg.cfg, pg.snk, hin, side, hout, batch)
+    sec = time.perf_counter() - t0
+    samples = F * n
+    res = {"workload": "the headline batch streamed from and to pinned host memory in batches of "
+                       f"{batch} frames (FIFOs hold two batches)",
+           "msamples_pcie_inclusive": round(samples / sec / 1e6, 1), "seconds": round(sec, 4),
+           "host_bytes_each_way": samples * 8,
+           "gb_per_s_each_way": round(samples * 8 / sec / 1e9, 2)}
+    del g, pg
+    torch.cuda.empty_cache()
     return res
 
 

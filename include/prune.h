@@ -362,6 +362,31 @@ prune_status prune_actor_reset_history(prune_graph_t g, prune_id actor, prune_st
 
 /* ---- external input / output -------------------------------------------- */
 
+/* Host actors beside device firings (the paper's heterogeneous execution,
+ * Sec. VI-C, with a source and sink on the CPU): stream n_frames frames
+ * from host memory through the graph and back, in batches of `batch`
+ * iterations, with three stages in flight at once:
+ *  - the frames of batch k+1 are copied from host_in into the source FIFO
+ *    (in place, on a copy stream of the library's),
+ *  - batch k fires (PRUNE_BATCHED on `stream`),
+ *  - the outputs of batch k-1 are copied from the sink's input FIFO to
+ *    host_out (on a second copy stream),
+ * ordered by events: a batch's frames go into ring blocks only after the
+ * batch that last read them has fired, and a batch fires only after the
+ * output blocks it overwrites have been copied out.  The result equals
+ * pushing every frame, firing and reading the sink.
+ * host_in: n_frames x atr tokens of the source FIFO, back to back; side:
+ * n_frames side-information records for `cfg`; host_out: n_frames x atr
+ * tokens of the sink's FIFO.  Pinned host memory (hipHostMalloc, torch
+ * pin_memory) lets the copies run concurrently with the firing; pageable
+ * memory works but serialises them.  Requirements: fixed-rate source and
+ * sink FIFOs without delay, the graph's C a multiple of `batch` holding at
+ * least two batches, no sink output bound, no pending source or side input.
+ * Returns when every output is on the host. */
+prune_status prune_graph_stream_host(prune_graph_t g, prune_id src, prune_id cfg, prune_id snk,
+                                     const void *host_in, const prune_side_info *side, void *host_out,
+                                     uint32_t n_frames, uint32_t batch, prune_stream_t stream);
+
 /* Queue n_frames firings of source `src`.  host_counts[f] = tokens of frame
  * f (equal to atr for an SRP, 1..atr for a PRUNE_PORT_PARAM port).
  * dev_samples: device pointer to the frames back to back (copied into the

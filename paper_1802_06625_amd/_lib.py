@@ -100,6 +100,8 @@ SIGNATURES = [
     ("prune_sink_bind_output", _ST, [_P, _ID, _P, C.c_uint64]),
     ("prune_graph_fire", _ST, [_P, C.c_int, C.c_uint32, _P, C.POINTER(C.c_uint64)]),
     ("prune_graph_sync", _ST, [_P, _P]),
+    ("prune_graph_stream_host", _ST, [_P, _ID, _ID, _ID, _P, C.POINTER(SideInfo), _P, C.c_uint32,
+                                      C.c_uint32, _P]),
     ("prune_fifo_get_stats", _ST, [_P, _ID, C.POINTER(FifoStats)]),
     ("prune_filterbank_branch_stats", _ST, [_P, _ID, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                             C.c_uint32]),

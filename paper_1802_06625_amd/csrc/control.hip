@@ -832,6 +832,7 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
     if (always && c.ports[ac.port].kind != PRUNE_DRP) {
       // an SRP of an actor that fires every iteration is accessed every iteration
       uint64_t loc = 0;
+#pragma unroll 8
       for (uint32_t i = tid; i < B; i += nt) {
         pre[i] = i;
         loc += cnt[i];
@@ -868,6 +869,7 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
     const bool fbk = kind == PRUNE_FILTERBANK;
     // total first, then the region, then the offsets
     uint32_t loc = 0;
+#pragma unroll 8
     for (uint32_t i = tid; i < B; i += nt) loc += b.s_aux[o + i];
     const uint64_t tot = block_sum_u64(loc, sm64);
     if (tid == 0) s_res = atomicAdd((fbk ? c.fb_count : c.copy_count) + lev, (uint32_t)tot);

@@ -206,13 +206,9 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
   if (timed) {
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    (void)hipEventRecord(e0, s);
   }
-  fb_forward_launch(variant, sc->desc, sc->items, sc->ctr, (unsigned int *)(sc->ctr + 1), grid, s);
-  if (timed) {
-    (void)hipEventRecord(e1, s);
-    timing_push(e0, e1);
-  }
+  fb_forward_launch(variant, sc->desc, sc->items, sc->ctr, (unsigned int *)(sc->ctr + 1), grid, s, e0, e1);
+  if (timed) timing_push(e0, e1);
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }
 }  // namespace prune

@@ -22,6 +22,8 @@
 // are zero.  Each lane computes J consecutive outputs from a register window
 // of 2J-1 samples per chunk of J taps; the tap coefficients of the chunk are
 // LDS broadcasts.
+#include <hip/hip_ext.h>
+
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
@@ -253,13 +255,20 @@ struct FbVariant {
   const char *name;
   int tile, WG;   // outputs per work item, threads per workgroup
   void (*launch)(const FbFrameDesc *, const WorkItem *, const uint32_t *, unsigned int *,
-                 uint32_t grid, hipStream_t);
+                 uint32_t grid, hipStream_t, hipEvent_t, hipEvent_t);
 };
 
+// With events, the dispatch itself records the kernel's start and end
+// (hipExtLaunchKernelGGL): no marker packets, no gaps around the kernel.
 template <int J, int WG, int WAVES>
 static void launch_fwd(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
-                       unsigned int *ticket, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_fb_forward<J, WG, WAVES>), dim3(grid), dim3(WG), 0, s, f, it, n, ticket);
+                       unsigned int *ticket, uint32_t grid, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL((k_fb_forward<J, WG, WAVES>), dim3(grid), dim3(WG), 0, s, e0, e1, 0, f, it, n,
+                          ticket);
+  else
+    hipLaunchKernelGGL((k_fb_forward<J, WG, WAVES>), dim3(grid), dim3(WG), 0, s, f, it, n, ticket);
 }
 
 static const FbVariant kVariants[] = {
@@ -283,8 +292,8 @@ int fb_variant_wg(int v) { return kVariants[v - 1].WG; }
 
 void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,
                        const uint32_t *n_items, unsigned int *ticket, uint32_t grid,
-                       hipStream_t s) {
-  kVariants[v - 1].launch(frames, items, n_items, ticket, grid, s);
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  kVariants[v - 1].launch(frames, items, n_items, ticket, grid, s, e0, e1);
 }
 
 }  // namespace prune

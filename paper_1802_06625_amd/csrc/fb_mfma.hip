@@ -26,6 +26,8 @@
 // one table read.  u_b is formed in registers from the window by repeated
 // multiplication with r.  Workgroups take tiles from the item list with an
 // atomic ticket, as the vector kernels do.
+#include <hip/hip_ext.h>
+
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
@@ -231,15 +233,21 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
 
 template <int NT, int NW>
 void launch_fb_mfma(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
-                    unsigned int *ticket, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_fb_mfma<NT, NW>), dim3(grid), dim3(64 * NW), 0, s, f, it, n, ticket);
+                    unsigned int *ticket, uint32_t grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL((k_fb_mfma<NT, NW>), dim3(grid), dim3(64 * NW), 0, s, e0, e1, 0, f, it, n, ticket);
+  else
+    hipLaunchKernelGGL((k_fb_mfma<NT, NW>), dim3(grid), dim3(64 * NW), 0, s, f, it, n, ticket);
 }
 
 template void launch_fb_mfma<4, 4>(const FbFrameDesc *, const WorkItem *, const uint32_t *,
-                                   unsigned int *, uint32_t, hipStream_t);
+                                   unsigned int *, uint32_t, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 template void launch_fb_mfma<2, 4>(const FbFrameDesc *, const WorkItem *, const uint32_t *,
-                                   unsigned int *, uint32_t, hipStream_t);
+                                   unsigned int *, uint32_t, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 template void launch_fb_mfma<4, 2>(const FbFrameDesc *, const WorkItem *, const uint32_t *,
-                                   unsigned int *, uint32_t, hipStream_t);
+                                   unsigned int *, uint32_t, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 
 }  // namespace prune

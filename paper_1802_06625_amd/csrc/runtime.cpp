@@ -720,14 +720,10 @@ void fb_launch_timed(prune_graph *g, uint32_t level, uint32_t grid, hipStream_t 
   if (g_timing) {
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    hipEventRecord(e0, s);
   }
   fb_forward_launch(g->variant, g->d_desc, g->d_items + g->fb_item_off[level], g->d_ctr + level,
-                    (unsigned int *)(g->d_ctr + 2 * nl + level), grid, s);
-  if (g_timing) {
-    hipEventRecord(e1, s);
-    g_events.push_back({e0, e1});
-  }
+                    (unsigned int *)(g->d_ctr + 2 * nl + level), grid, s, e0, e1);
+  if (g_timing) g_events.push_back({e0, e1});
 }
 
 // Launch the data kernels of one level (halo gathers first: they read input
@@ -1418,6 +1414,114 @@ prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings, p
     if (max_firings && done >= max_firings) break;
   }
   if (fired) *fired = done;
+  return PRUNE_OK;
+}
+
+prune_status prune_graph_stream_host(prune_graph_t g, prune_id src, prune_id cfg, prune_id snk,
+                                     const void *host_in, const prune_side_info *side, void *host_out,
+                                     uint32_t n_frames, uint32_t batch, prune_stream_t stream) {
+  TRY(check_graph(g, true));
+  if (src >= g->actors.size() || g->actors[src].kind != PRUNE_SOURCE || cfg >= g->actors.size() ||
+      g->actors[cfg].kind != PRUNE_CONFIG || snk >= g->actors.size() || g->actors[snk].kind != PRUNE_SINK)
+    return fail(PRUNE_E_ARG, "src, cfg and snk must be a source, a configuration actor and a sink");
+  if (n_frames && (!host_in || !side || !host_out)) return fail(PRUNE_E_ARG, "null host buffer");
+  HActor &S = g->actors[src], &Q = g->actors[cfg], &K = g->actors[snk];
+  const uint32_t fi = g->ports[S.ports[0]].fifos.at(0);
+  uint32_t fo = kNone;
+  for (uint32_t p : K.ports)
+    if (g->ports[p].dir == PRUNE_IN && g->ports[p].kind != PRUNE_CPORT) fo = g->ports[p].fifos.at(0);
+  if (fo == kNone || g->ports[S.ports[0]].fifos.size() != 1) return fail(PRUNE_E_ARG, "source or sink not connected");
+  const HFifo &Fi = g->fifos[fi], &Fo = g->fifos[fo];
+  if (Fi.param || Fo.param || Fi.delay || Fo.delay)
+    return fail(PRUNE_E_UNSUPPORTED, "host streaming needs fixed-rate source and sink FIFOs without delay");
+  if (!batch || g->C % batch || g->C < 2 * batch)
+    return fail(PRUNE_E_ARG, "C must be a multiple of the batch and hold at least two batches");
+  if (K.sink_out) return fail(PRUNE_E_STATE, "the sink must not have an output buffer bound");
+  if (!S.src_q.empty() || !Q.side_q.empty()) return fail(PRUNE_E_STATE, "pending source or side input");
+  if (!n_frames) return PRUNE_OK;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipStreamSynchronize(s));
+  HIPCHECK(hipDeviceSynchronize());
+  FifoDev di, dout;
+  HIPCHECK(hipMemcpy(&di, g->d_fifos + fi, sizeof di, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(&dout, g->d_fifos + fo, sizeof dout, hipMemcpyDeviceToHost));
+  // every frame's side-information and (in-place) source entry up front
+  std::vector<uint32_t> counts(n_frames, Fi.rate);
+  TRY(prune_config_push(g, cfg, side, n_frames, stream));
+  TRY(prune_source_push(g, src, nullptr, counts.data(), n_frames));
+
+  const uint32_t depth = g->C / batch;   // batches the ring holds
+  const uint32_t nb = (n_frames + batch - 1) / batch;
+  const size_t bi = (size_t)Fi.rate * Fi.token_bytes, bo = (size_t)Fo.rate * Fo.token_bytes;
+  hipStream_t h2d = nullptr, d2h = nullptr;
+  std::vector<hipEvent_t> ev(3 * nb, nullptr);
+  prune_status st = PRUNE_OK;
+  auto cleanup = [&]() {
+    if (h2d) (void)hipStreamSynchronize(h2d);
+    if (d2h) (void)hipStreamSynchronize(d2h);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h2d) (void)hipStreamDestroy(h2d);
+    if (d2h) (void)hipStreamDestroy(d2h);
+  };
+  // Copies of a run of blocks of a ring, split where the ring wraps.
+  auto copy_blocks = [&](char *ring, uint64_t first, uint32_t n, size_t blk, char *host, bool to_dev,
+                         hipStream_t cs) -> hipError_t {
+    uint32_t done = 0;
+    while (done < n) {
+      const uint64_t slot = (first + done) % g->C;
+      const uint32_t run = (uint32_t)std::min<uint64_t>(n - done, g->C - slot);
+      char *dev = ring + slot * blk;
+      char *h = host + (size_t)done * blk;
+      hipError_t e = to_dev ? hipMemcpyAsync(dev, h, (size_t)run * blk, hipMemcpyHostToDevice, cs)
+                            : hipMemcpyAsync(h, dev, (size_t)run * blk, hipMemcpyDeviceToHost, cs);
+      if (e != hipSuccess) return e;
+      done += run;
+    }
+    return hipSuccess;
+  };
+  if (hipStreamCreateWithFlags(&h2d, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&d2h, hipStreamNonBlocking) != hipSuccess) {
+    cleanup();
+    return fail(PRUNE_E_HIP, "stream creation failed");
+  }
+  for (auto &e : ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(PRUNE_E_HIP, "event creation failed");
+    }
+  for (uint32_t k = 0; k < nb && st == PRUNE_OK; ++k) {
+    const uint32_t nk = std::min(batch, n_frames - k * batch);
+    hipEvent_t e_in = ev[3 * k], e_fired = ev[3 * k + 1], e_out = ev[3 * k + 2];
+    // frames of batch k into the source FIFO once the batch that last read
+    // those blocks has fired
+    if (k >= depth && hipStreamWaitEvent(h2d, ev[3 * (k - depth) + 1], 0) != hipSuccess) st = PRUNE_E_HIP;
+    if (st == PRUNE_OK &&
+        copy_blocks((char *)Fi.storage, di.writes + (uint64_t)k * batch, nk, bi,
+                    (char *)host_in + (size_t)k * batch * bi, true, h2d) != hipSuccess)
+      st = PRUNE_E_HIP;
+    if (st == PRUNE_OK && hipEventRecord(e_in, h2d) != hipSuccess) st = PRUNE_E_HIP;
+    // fire batch k once its frames are in and the output blocks it will
+    // overwrite have been copied out
+    if (st == PRUNE_OK && hipStreamWaitEvent(s, e_in, 0) != hipSuccess) st = PRUNE_E_HIP;
+    if (st == PRUNE_OK && k >= depth && hipStreamWaitEvent(s, ev[3 * (k - depth) + 2], 0) != hipSuccess)
+      st = PRUNE_E_HIP;
+    uint64_t fired = 0;
+    if (st == PRUNE_OK) st = prune_graph_fire(g, PRUNE_BATCHED, nk, stream, &fired);
+    if (st == PRUNE_OK && fired != nk) st = fail(PRUNE_E_STATE, "a batch fired fewer iterations than queued");
+    if (st == PRUNE_OK && hipEventRecord(e_fired, s) != hipSuccess) st = PRUNE_E_HIP;
+    // outputs of batch k to the host
+    if (st == PRUNE_OK && hipStreamWaitEvent(d2h, e_fired, 0) != hipSuccess) st = PRUNE_E_HIP;
+    if (st == PRUNE_OK &&
+        copy_blocks((char *)Fo.storage, dout.reads + (uint64_t)k * batch, nk, bo,
+                    (char *)host_out + (size_t)k * batch * bo, false, d2h) != hipSuccess)
+      st = PRUNE_E_HIP;
+    if (st == PRUNE_OK && hipEventRecord(e_out, d2h) != hipSuccess) st = PRUNE_E_HIP;
+  }
+  cleanup();
+  if (st == PRUNE_E_HIP) return fail(PRUNE_E_HIP, "host streaming: HIP call failed");
+  if (st != PRUNE_OK) return st;
+  HIPCHECK(hipStreamSynchronize(s));
   return PRUNE_OK;
 }
 

@@ -90,14 +90,15 @@ void launch_copyback(const CtrlArgs &c, uint32_t a, uint32_t fifo, uint32_t k, h
 
 template <int NT, int NW>
 void launch_fb_mfma(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
-                    unsigned int *ticket, uint32_t grid, hipStream_t s);
+                    unsigned int *ticket, uint32_t grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 int fb_variant_count();
 const char *fb_variant_name(int v);
 int fb_variant_tile(int v);
 int fb_variant_wg(int v);
+// e0/e1 (may be null): events that receive the kernel's own start and end.
 void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,
                        const uint32_t *n_items, unsigned int *ticket, uint32_t grid,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Direct-op helpers.
 void launch_direct_prep(const prune_fb_desc &d, const float2 *x, const float2 *taps,

@@ -162,6 +162,14 @@ class Graph:
         call("prune_config_push", self.h, cfg, side.ctypes.data_as(C.POINTER(L.SideInfo)), len(side),
              _stream(stream))
 
+    def stream_host(self, src, cfg, snk, host_in, side, host_out, batch, stream=None):
+        """prune_graph_stream_host: frames from a (pinned) host tensor through
+        the graph and back into a host tensor, copies overlapped with firing."""
+        side = np.ascontiguousarray(side, dtype=np.uint32).reshape(-1, 4)
+        call("prune_graph_stream_host", self.h, src, cfg, snk, C.c_void_p(host_in.data_ptr()),
+             side.ctypes.data_as(C.POINTER(L.SideInfo)), C.c_void_p(host_out.data_ptr()), len(side),
+             int(batch), _stream(stream))
+
     def sink_bind_output(self, snk, tensor):
         self._keep.append(tensor)
         call("prune_sink_bind_output", self.h, snk, C.c_void_p(tensor.data_ptr()), tensor.numel())

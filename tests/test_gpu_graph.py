@@ -256,3 +256,29 @@ def test_plain_arbitrary_branch_sets(mode):
     bf, bt = dev["g"].branch_stats(dev["pg"].fb, wl.Kmax)
     assert bf == logs_ref["actors"][ids["fb"]]["branch_firings"]
     assert bt == logs_ref["actors"][ids["fb"]]["branch_tokens"]
+
+
+# ---------------------------------------------------------------- host source and sink
+@pytest.mark.parametrize("batch,C", [(16, 32), (16, 48), (20, 40)])
+def test_host_stream(batch, C):
+    """Frames from pinned host memory through the graph and back with the
+    copies overlapped (prune_graph_stream_host): equal to the oracle over the
+    whole stream, also when the stream is fed in two calls whose batches wrap
+    around the FIFO rings."""
+    announce(f"host stream batch={batch} C={C}")
+    from paper_1802_06625_amd.graph import PlainGraph
+    wl = synth.make("C1")
+    y_ref, _, _, _ = og.run_plain(wl, C=3)
+    n = wl.side[0, :, 1]
+    atr = int(n[0])
+    pg = PlainGraph(wl.Kmax, wl.bank_L, atr, C)
+    pg.g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    hin = torch.from_numpy(wl.x[0]).pin_memory()
+    hout = torch.zeros(hin.shape, dtype=hin.dtype).pin_memory()
+    half = 28 * atr
+    pg.g.stream_host(pg.src, pg.cfg, pg.snk, hin[:half], wl.side[0, :28], hout[:half], batch)
+    pg.g.stream_host(pg.src, pg.cfg, pg.snk, hin[half:], wl.side[0, 28:], hout[half:], batch)
+    assert rel_l2(hout.numpy(), y_ref) <= TOL
+    with pytest.raises(L.PruneError) as e:
+        pg.g.stream_host(pg.src, pg.cfg, pg.snk, hin, wl.side[0], hout, C)   # one batch only
+    assert e.value.code == L.E_ARG
