@@ -6,7 +6,8 @@ capacity of Eq. 2 and the delay access pattern of Fig. 6, control tokens
 decoded per Eq. 1, blocking firing rules, a round-robin scheduler with
 deadlock detection, per-firing logs), the compile-time analysis of Sec. IV-V
 (design rules, DPGs and their dynamic components, per-component consistency
-and buffer bounds), the memory-polynomial filter-bank actor
+and buffer bounds), the Motion Detection actors (Gauss 5x5, frame-difference threshold,
+5-pixel median), the memory-polynomial filter-bank actor
 by its direct definition, its adjoint in closed form, finite differences and
 the least-squares / Adam fit.
 
@@ -24,6 +25,6 @@ from .moc import (PruneError, Graph, E_ARG, E_STATE, E_RATE_MISMATCH, E_PORT_KIN
                   FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK, POLY, FIR, ADD,
                   fifo_capacity, fifo_write_slot, fifo_read_slot)
 from .filterbank import (fb_frame, fb_stream, fb_stream_adjoint, basis)
-from . import graphs, fit, analysis
+from . import graphs, fit, analysis, motion
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -10,6 +10,9 @@
            stateless, as the design rules require of DC actors).
 * unfused: SOURCE -> POLY (x) -> FIR_b -> ADD (y) -> SINK, CONFIG -> POLY, ADD:
            the DPD graph of Fig. 8 before actor merging.
+* motion:  SOURCE -> GAUSS5 -> THRES -> MED5 -> SINK on uint8 frames (Fig. 7);
+           GAUSS5's output port feeds THRES twice, the second FIFO with a
+           one-frame delay (the previous frame of the difference).
 
 Parity: exercised by tests/test_oracle_moc.py (fused == unfused, token
 conservation, schedule independence, frame-split invariance).
@@ -20,7 +23,7 @@ import numpy as np
 
 from . import moc
 from .moc import (Graph, IN, OUT, SRP, DRP, CPORT, SOURCE, CONFIG, FILTERBANK,
-                  SWITCH, SELECT, PASSTHROUGH, SINK, POLY, FIR, ADD)
+                  SWITCH, SELECT, PASSTHROUGH, SINK, POLY, FIR, ADD, GAUSS5, THRES, MED5)
 
 
 def _frames_of(wl, s):
@@ -178,3 +181,40 @@ def stream_frames(wl, s=0):
             route = 0
         out.append((int(off[f]), n, mask, route))
     return out
+
+
+def build_motion(W, H, C, T=20):
+    """Motion Detection graph (Sec. VII-A): a frame is W*H one-byte tokens."""
+    npix = W * H
+    g = Graph()
+    src = g.actor(SOURCE)
+    gau = g.actor(GAUSS5, W=W, H=H)
+    thr = g.actor(THRES, W=W, H=H, T=T)
+    med = g.actor(MED5, W=W, H=H)
+    snk = g.actor(SINK)
+    p_src = g.port(src, OUT, SRP, npix, u8=True)
+    p_gi = g.port(gau, IN, SRP, npix, u8=True)
+    p_go = g.port(gau, OUT, SRP, npix, u8=True)
+    p_tc = g.port(thr, IN, SRP, npix, u8=True)
+    p_tp = g.port(thr, IN, SRP, npix, u8=True)
+    p_to = g.port(thr, OUT, SRP, npix, u8=True)
+    p_mi = g.port(med, IN, SRP, npix, u8=True)
+    p_mo = g.port(med, OUT, SRP, npix, u8=True)
+    p_snk = g.port(snk, IN, SRP, npix, u8=True)
+    g.connect(p_src, p_gi, npix)
+    g.connect(p_go, p_tc, npix)
+    g.connect(p_go, p_tp, npix, npix)     # one-frame delay: the previous frame
+    g.connect(p_to, p_mi, npix)
+    g.connect(p_mo, p_snk, npix)
+    g.finalize(C)
+    return g, dict(src=src, gauss=gau, thres=thr, med=med, snk=snk)
+
+
+def run_motion(frames, C=3, T=20):
+    """Run the Motion Detection graph over uint8 frames [F, H, W]; returns
+    (motion maps [F, H, W], logs, g, ids)."""
+    F, H, W = frames.shape
+    g, ids = build_motion(W, H, C, T)
+    g.push(ids["src"], [fr.ravel() for fr in frames])
+    g.run()
+    return g.sink_output(ids["snk"]).reshape(F, H, W), g.logs(), g, ids

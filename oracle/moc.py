@@ -35,6 +35,7 @@ from __future__ import annotations
 import numpy as np
 
 from .filterbank import fb_frame, basis
+from .motion import gauss5, thres, med5
 
 # Status codes (names match the C library's; values are the library's too).
 E_ARG, E_STATE, E_RATE_MISMATCH, E_PORT_KIND, E_RULE4, E_CONNECT = -1, -2, -3, -4, -5, -6
@@ -43,9 +44,10 @@ E_DELAY, E_TOKEN, E_DEADLOCK, E_CAPACITY, E_HIP, E_UNSUPPORTED = -7, -8, -9, -10
 IN, OUT, INTERNAL = 0, 1, 2
 SRP, DRP, CPORT = 0, 1, 2
 (SOURCE, CONFIG, FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK,
- POLY, FIR, ADD) = range(10)
+ POLY, FIR, ADD, GAUSS5, THRES, MED5) = range(13)
 KIND_NAMES = ["SOURCE", "CONFIG", "FILTERBANK", "SWITCH", "SELECT", "PASSTHROUGH",
-              "SINK", "POLY", "FIR", "ADD"]
+              "SINK", "POLY", "FIR", "ADD", "GAUSS5", "THRES", "MED5"]
+PIXEL_KINDS = (GAUSS5, THRES, MED5)   # Motion Detection actors on uint8 frames
 
 
 class PruneError(Exception):
@@ -176,11 +178,12 @@ class FifoState:
 # --------------------------------------------------------------------------
 
 class Port:
-    __slots__ = ("id", "actor", "dir", "kind", "atr", "param", "halo", "fifos")
+    __slots__ = ("id", "actor", "dir", "kind", "atr", "param", "halo", "fifos", "u8")
 
-    def __init__(self, pid, actor, dir, kind, atr, param, halo):
+    def __init__(self, pid, actor, dir, kind, atr, param, halo, u8=False):
         self.id, self.actor, self.dir, self.kind = pid, actor, dir, kind
         self.atr, self.param, self.halo = atr, param, halo
+        self.u8 = u8             # one-byte tokens (pixels) instead of complex samples
         self.fifos = []
 
 
@@ -214,7 +217,7 @@ class Graph:
 
     def actor(self, kind, **params) -> int:
         self._check_open()
-        if kind not in range(10):
+        if kind not in range(13):
             raise PruneError(E_ARG, f"unknown actor kind {kind}")
         a = Actor(len(self.actors), kind, dict(params))
         self.actors.append(a)
@@ -231,14 +234,14 @@ class Graph:
                 a.branches.append(pid)
         return a.id
 
-    def port(self, aid, dir, kind, atr, param=False, halo=0) -> int:
+    def port(self, aid, dir, kind, atr, param=False, halo=0, u8=False) -> int:
         self._check_open()
         if not (0 <= aid < len(self.actors)) or dir not in (IN, OUT) or kind not in (SRP, DRP, CPORT):
             raise PruneError(E_ARG, "bad port arguments")
         if atr <= 0:
             raise PruneError(E_ARG, "atr must be positive")
         pid = len(self.ports)
-        self.ports.append(Port(pid, aid, dir, kind, int(atr), bool(param), int(halo)))
+        self.ports.append(Port(pid, aid, dir, kind, int(atr), bool(param), int(halo), bool(u8)))
         self.actors[aid].ports.append(pid)
         return pid
 
@@ -306,6 +309,8 @@ class Graph:
                 raise PruneError(E_RATE_MISMATCH, f"fifo {fid}: rate parameterisation differs")
             if ps.param and Q:
                 raise PruneError(E_DELAY, f"fifo {fid}: delay on a parameterised FIFO")
+            if ps.u8 != pd.u8:
+                raise PruneError(E_RATE_MISMATCH, f"fifo {fid}: token types differ")
             if Q % rate and (Q >= rate * C or (Q < rate and Q + rate > rate * C)):
                 raise PruneError(E_DELAY, f"fifo {fid}: unaligned delay does not fit r*C")
             if (pd.kind == CPORT) != (self.actors[ps.actor].kind == CONFIG):
@@ -394,6 +399,13 @@ class Graph:
                      E_RATE_MISMATCH, "output window = input + halo")
             if k == POLY:
                 need(len(outs) == a.params["Kmax"], E_ARG, "one output per branch")
+        elif k in PIXEL_KINDS:
+            npix = a.params["W"] * a.params["H"]
+            need(len(data_in) == (2 if k == THRES else 1) and len(outs) == 1, E_ARG,
+                 "pixel actors: one input (two for THRES), one output")
+            for p in data_in + outs:
+                need(p.atr == npix and p.u8 and not p.param and not p.halo, E_RATE_MISMATCH,
+                     "pixel ports carry one W*H frame of one-byte tokens")
         elif k in (SELECT, ADD):
             need(len(outs) == 1 and outs[0].kind == SRP and in_drp and len(in_drp) == len(data_in),
                  E_ARG, "DRP inputs, one SRP output")
@@ -406,7 +418,7 @@ class Graph:
         self.fstate = []
         for fid, (s, d, rate, Q) in enumerate(self.fifos):
             ctrl = self.ports[d].kind == CPORT
-            dt = CTRL_DTYPE if ctrl else np.complex128
+            dt = CTRL_DTYPE if ctrl else (np.uint8 if self.ports[s].u8 else np.complex128)
             self.fstate.append(FifoState(fid, rate, Q, self.C, dt, self.ports[s].param))
         for a in self.actors:
             a.firings = 0
@@ -435,7 +447,9 @@ class Graph:
         configuration actor (array [F, 4] of side-information K, n, bank, route)."""
         a = self.actors[aid]
         if a.kind == SOURCE:
-            a.state["queue"].extend(np.asarray(f, np.complex128) for f in frames)
+            u8 = self._ports(aid, OUT)[0].u8
+            a.state["queue"].extend(np.asarray(f, np.uint8 if u8 else np.complex128).ravel()
+                                    for f in frames)
         elif a.kind == CONFIG:
             a.state["queue"].extend(np.asarray(frames, np.int64).reshape(-1, 4))
         else:
@@ -589,6 +603,17 @@ class Graph:
         if k == SINK:
             a.state["out"].append(data[ins_c[0][0].id])
             return res
+        if k in PIXEL_KINDS:
+            shape = (a.params["H"], a.params["W"])
+            frames = [data[p.id].reshape(shape) for p, c in ins_c]
+            if k == GAUSS5:
+                y = gauss5(frames[0])
+            elif k == MED5:
+                y = med5(frames[0])
+            else:
+                y = thres(frames[0], frames[1], a.params.get("T", 20))
+            res[outs_c[0][0].id] = y.ravel()
+            return res
         if k == PASSTHROUGH:
             res[outs_c[0][0].id] = data[ins_c[0][0].id]
             return res
@@ -693,7 +718,10 @@ class Graph:
     # ---- results -------------------------------------------------------------
     def sink_output(self, aid):
         out = self.actors[aid].state["out"]
-        return np.concatenate(out) if out else np.zeros(0, np.complex128)
+        if not out:
+            u8 = self._ports(aid, IN)[0].u8
+            return np.zeros(0, np.uint8 if u8 else np.complex128)
+        return np.concatenate(out)
 
     def logs(self):
         """Canonical integer logs (compared bit-exactly with the device)."""

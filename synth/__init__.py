@@ -200,3 +200,40 @@ def scaled(name: str, seed: int = 0, **kw) -> Workload:
     }[name]
     small.update(kw)
     return make(name, seed=seed, **small)
+
+
+def make_video(n_frames: int, width: int = 1920, height: int = 1080, seed: int = 0,
+               n_objects: int = 4) -> np.ndarray:
+    """Synthetic 8-bit grayscale video standing in for the 1080p sequence
+    of the paper's Motion Detection run: a static textured background (a
+    sum of a few random planar cosines), bright or dark rectangles moving
+    at constant random velocities, and per-frame Gaussian noise (sigma 3).
+    Returns uint8 [n_frames, height, width].  Draw order: background
+    waves, then objects (size, position, velocity, level), then noise per
+    frame."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed + 1000)))
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float32)
+    bg = np.full((height, width), 120.0, np.float32)
+    for _ in range(3):
+        fx, fy = g.uniform(0.002, 0.02, size=2)
+        ph = g.uniform(0, 2 * np.pi)
+        bg += g.uniform(10, 30) * np.cos(2 * np.pi * (fx * xx + fy * yy) + ph).astype(np.float32)
+    objs = []
+    for _ in range(n_objects):
+        w = int(g.integers(width // 20, width // 6))
+        h = int(g.integers(height // 20, height // 6))
+        x0 = float(g.uniform(0, width - w))
+        y0 = float(g.uniform(0, height - h))
+        vx, vy = g.uniform(-12, 12, size=2)
+        level = float(g.choice([-1.0, 1.0]) * g.uniform(40, 80))
+        objs.append((w, h, x0, y0, vx, vy, level))
+    out = np.empty((n_frames, height, width), np.uint8)
+    for f in range(n_frames):
+        fr = bg.copy()
+        for (w, h, x0, y0, vx, vy, level) in objs:
+            x = int(round(x0 + vx * f)) % (width - w)
+            y = int(round(y0 + vy * f)) % (height - h)
+            fr[y:y + h, x:x + w] += level
+        fr += g.normal(0.0, 3.0, size=fr.shape).astype(np.float32)
+        out[f] = np.clip(np.rint(fr), 0, 255).astype(np.uint8)
+    return out
