@@ -101,6 +101,21 @@ enum { PRUNE_PORT_PARAM = 1u };
  *              a SWITCH whose k-th output port (creation order, k = 0..)
  *              carries the basis u_{k+1} = |x|^k x of the window (halo
  *              included), so output k feeds the FIR of branch k+1.
+ *  GAUSS5, THRES, MED5  the static actors of the Motion Detection graph
+ *              (Sec. VII-A, Fig. 7) on 8-bit frames (prune_pixel_params; a
+ *              frame is W*H one-byte tokens, token_bytes 1, one frame per
+ *              firing):
+ *                GAUSS5 out = (sum_{dy,dx} w_dy w_dx in[y+dy][x+dx] + 128) >> 8
+ *                       with w = (1 4 6 4 1), rows 2..H-3 (the two rows at
+ *                       each end are copied), columns clamped at the edges;
+ *                THRES  two inputs (current, previous frame): 255 where
+ *                       |cur - prev| > threshold, else 0;
+ *                MED5   median of the pixel and its up, down, left and right
+ *                       neighbours, rows 1..H-2 (rows 0 and H-1 copied),
+ *                       columns clamped.
+ *              The previous frame reaches THRES through a FIFO with a delay
+ *              of W*H tokens (one frame of zeros).  SOURCE and SINK carry
+ *              such frames with token_bytes 1 (W*H a multiple of 8).
  * Limits: at most PRUNE_MAX_PORTS ports per actor, PRUNE_MAX_IN data
  * inputs, PRUNE_MAX_IO output FIFO accesses per firing. */
 enum {
@@ -111,7 +126,10 @@ enum {
   PRUNE_SELECT = 4,
   PRUNE_PASSTHROUGH = 5,
   PRUNE_SINK = 6,
-  PRUNE_POLY = 7
+  PRUNE_POLY = 7,
+  PRUNE_GAUSS5 = 8,
+  PRUNE_THRES = 9,
+  PRUNE_MED5 = 10
 };
 enum { PRUNE_MAX_PORTS = 14, PRUNE_MAX_IN = 10, PRUNE_MAX_IO = 12 };
 
@@ -156,6 +174,11 @@ typedef struct {
   uint32_t Kmax;       /* branches per bank (prefix mode)                    */
   uint32_t n_elements; /* |v|: number of elements of the control value      */
 } prune_config_params;
+
+typedef struct {
+  uint32_t W, H;        /* frame width and height in pixels (W*H = the rate)  */
+  uint32_t threshold;   /* THRES: difference threshold (the paper's constant) */
+} prune_pixel_params;
 
 #define PRUNE_MAX_BANKS 4
 #define PRUNE_MAX_BRANCHES 32 /* n_banks * Kmax <= 32 (one mask word)     */

@@ -22,7 +22,7 @@ AN_LINKED, AN_DPGS, AN_DCS, AN_DC_ACTORS, AN_ACTOR_DC, AN_BETA, AN_VIOLATIONS = 
 IN, OUT = 0, 1
 SRP, DRP, CPORT = 0, 1, 2
 PORT_PARAM = 1
-SOURCE, CONFIG, FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK, POLY = range(8)
+SOURCE, CONFIG, FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK, POLY, GAUSS5, THRES, MED5 = range(11)
 MAX_PORTS, MAX_IN, MAX_IO = 14, 10, 12
 PER_FIRING, BATCHED, BATCHED_GRAPH = 0, 1, 2
 CONFIG_PREFIX, CONFIG_ROUTE, CONFIG_MASK = 0, 1, 2
@@ -39,6 +39,10 @@ class SideInfo(C.Structure):
 
 class ConfigParams(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("Kmax", C.c_uint32), ("n_elements", C.c_uint32)]
+
+
+class PixelParams(C.Structure):
+    _fields_ = [("W", C.c_uint32), ("H", C.c_uint32), ("threshold", C.c_uint32)]
 
 
 class FbParams(C.Structure):

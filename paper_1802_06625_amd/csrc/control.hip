@@ -351,7 +351,8 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
       if (tid == 0) { fb->branch_firings[dd] += fi; fb->branch_tokens[dd] += tk; }
     }
   } else if (kind == PRUNE_SWITCH || kind == PRUNE_POLY || kind == PRUNE_SELECT ||
-             kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK) {
+             kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK ||
+             kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
     // Items are counted first, then written in place at their scanned
     // offsets (a per-lane array of items, indexed by slot, would live in
     // scratch).
@@ -378,7 +379,8 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
       float2 *sink_dst = nullptr;
       if (kind == PRUNE_SINK && nitems) {
         const uint64_t off = A.sink_pos + pre_tok;
-        if (off + sink_tok <= A.sink_cap) sink_dst = A.sink_out + off;
+        const uint32_t tb = c.fifos[R[i].in[0].fifo].token_bytes;
+        if (off + sink_tok <= A.sink_cap) sink_dst = (float2 *)((char *)A.sink_out + off * tb);
         else { nitems = 0; atomicOr(c.err, kErrCount); }
       }
       uint32_t tot;
@@ -398,7 +400,11 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
         ci.halo_count = 0;
         ci.count = count;
         ci.pad = 0;
+        ci.op = kOpCopy; ci.width = 0; ci.param = 0; ci.pad2 = 0;
         return ci;
+      };
+      auto words = [&](uint32_t fifo, uint32_t count) -> uint32_t {
+        return fifo == kNone ? count : count * c.fifos[fifo].token_bytes / 8u;
       };
       if (nitems) {
         if (kind == PRUNE_SWITCH || kind == PRUNE_POLY) {
@@ -413,13 +419,25 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
           }
         } else if (kind == PRUNE_SOURCE) {
           for (uint32_t k = 0; k < out_slot; ++k)
-            item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[k].ptr, R[i].out[k].count);
+            item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[k].ptr,
+                 words(R[i].out[k].fifo, R[i].out[k].count));
         } else if (kind == PRUNE_SINK) {
-          item((const float2 *)R[i].in[0].ptr, sink_dst, R[i].in[0].count);
+          item((const float2 *)R[i].in[0].ptr, sink_dst, words(R[i].in[0].fifo, R[i].in[0].count));
+        } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
+          for (uint32_t k = 0; k < out_slot; ++k) {   // one item per output access (broadcast)
+            CopyItem &ci = item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[k].ptr, A.pix_w * A.pix_h);
+            if (kind == PRUNE_THRES) {
+              ci.src[1] = (const float2 *)R[i].in[1].ptr;
+              ci.n_src = 2;
+            }
+            ci.op = kind == PRUNE_GAUSS5 ? kOpGauss5 : (kind == PRUNE_THRES ? kOpThres : kOpMed5);
+            ci.width = A.pix_w;
+            ci.param = A.pix_t;
+          }
         } else {
           // SELECT sums its active inputs; PASSTHROUGH copies its input.
           for (uint32_t k = 0; k < out_slot; ++k) {
-            CopyItem &ci = item(nullptr, (float2 *)R[i].out[k].ptr, R[i].out[k].count);
+            CopyItem &ci = item(nullptr, (float2 *)R[i].out[k].ptr, words(R[i].out[k].fifo, R[i].out[k].count));
             uint32_t ns = 0;
             for (int q = 0; q < kMaxIn; ++q)
               if (R[i].in[q].ptr) ci.src[ns++] = (const float2 *)R[i].in[q].ptr;
@@ -454,9 +472,55 @@ __global__ __launch_bounds__(1024) void k_control(CtrlArgs c) {
 // the level, y over chunks of kCopyChunk samples.
 constexpr uint32_t kCopyChunk = 4096;
 
-// Items with a nonzero power (POLY outputs) store |v|^power * v.  The item
-// is staged in LDS so that its source list is indexed there rather than in
-// per-lane scratch.
+// Median of five values: a sorting network on the low three after
+// discarding the two extremes of pairs.
+__device__ inline uint32_t median5(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
+  // order (a, b) and (c, d), drop the smaller of the two minima and the
+  // larger of the two maxima: the median of five is the median of the rest
+  if (a > b) { const uint32_t t = a; a = b; b = t; }
+  if (c > d) { const uint32_t t = c; c = d; d = t; }
+  if (a < c) { a = e; if (a > b) { const uint32_t t = a; a = b; b = t; } }
+  else       { c = e; if (c > d) { const uint32_t t = c; c = d; d = t; } }
+  if (a < c) return b < c ? b : c;
+  return d < a ? d : a;
+}
+
+// One pixel of a Motion Detection actor.  src/dst are byte frames of W
+// columns and H rows; k = y*W + x.
+__device__ inline uint32_t pixel_op(uint32_t op, const uint8_t *a, const uint8_t *b, uint32_t k,
+                                    int W, int H, uint32_t T) {
+  const int y = (int)(k / (uint32_t)W), x = (int)(k - (uint32_t)y * W);
+  if (op == kOpThres) {
+    const int d = (int)a[k] - (int)b[k];
+    return (uint32_t)(d > (int)T || -d > (int)T) * 255u;
+  }
+  if (op == kOpGauss5) {
+    if (y < 2 || y > H - 3) return a[k];
+    const uint32_t w[5] = {1, 4, 6, 4, 1};
+    int xs[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) xs[q] = min(max(x + q - 2, 0), W - 1);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int dy = 0; dy < 5; ++dy) {
+      const uint8_t *row = a + (size_t)(y + dy - 2) * W;
+      uint32_t h = 0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) h += w[q] * row[xs[q]];
+      acc += w[dy] * h;
+    }
+    return (acc + 128u) >> 8;
+  }
+  // kOpMed5
+  if (y < 1 || y > H - 2) return a[k];
+  const uint8_t *row = a + (size_t)y * W;
+  return median5(row[x], row[x - W], row[x + W], row[max(x - 1, 0)], row[min(x + 1, W - 1)]);
+}
+
+// Items with a nonzero power (POLY outputs) store |v|^power * v; pixel
+// items (op != kOpCopy) run a Motion Detection actor over a byte frame.  The
+// item is staged in LDS so that its source list is indexed there rather
+// than in per-lane scratch.
 __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items,
                                               const uint32_t *__restrict__ n_items) {
   __shared__ CopyItem s_ci;
@@ -470,6 +534,15 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
     const uint32_t lo = blockIdx.y * kCopyChunk;
     if (lo >= total) continue;
     const uint32_t hi = min(total, lo + kCopyChunk);
+    if (s_ci.op != kOpCopy) {
+      const uint8_t *a = (const uint8_t *)s_ci.src[0];
+      const uint8_t *b = (const uint8_t *)s_ci.src[1];
+      uint8_t *o = (uint8_t *)s_ci.dst;
+      const int W = (int)s_ci.width, H = (int)(s_ci.count / s_ci.width);
+      const uint32_t op = s_ci.op, T = s_ci.param;
+      for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) o[k] = (uint8_t)pixel_op(op, a, b, k, W, H, T);
+      continue;
+    }
     float2 *dst = s_ci.dst;
     for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
       float2 v;
@@ -477,11 +550,15 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
         v = s_ci.halo[k];
       } else {
         const uint32_t s = k - halo_count;
-        v = make_float2(0.f, 0.f);
-        for (uint32_t q = 0; q < n_src; ++q) {
-          const float2 u = s_ci.src[q][s];
-          v.x += u.x;
-          v.y += u.y;
+        if (n_src == 1) {
+          v = s_ci.src[0][s];   // a copy moves the bits (byte frames too), no arithmetic
+        } else {
+          v = make_float2(0.f, 0.f);
+          for (uint32_t q = 0; q < n_src; ++q) {
+            const float2 u = s_ci.src[q][s];
+            v.x += u.x;
+            v.y += u.y;
+          }
         }
       }
       if (power) {
@@ -681,7 +758,8 @@ __global__ __launch_bounds__(256) void k_batch_decode(CtrlArgs c, BatchArgs b) {
         aux = src_ptr ? n_out : 0;
       } else if (kind == PRUNE_SINK) {
         aux = A.sink_out ? 1 : 0;
-      } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
+      } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH || kind == PRUNE_GAUSS5 ||
+                 kind == PRUNE_THRES || kind == PRUNE_MED5) {
         aux = n_out;
       }
     }
@@ -863,7 +941,8 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
 
   if (task == 1) {
     if (!(kind == PRUNE_FILTERBANK || kind == PRUNE_SWITCH || kind == PRUNE_POLY || kind == PRUNE_SELECT ||
-          kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK))
+          kind == PRUNE_PASSTHROUGH || kind == PRUNE_SOURCE || kind == PRUNE_SINK || kind == PRUNE_GAUSS5 ||
+          kind == PRUNE_THRES || kind == PRUNE_MED5))
       return;
     const uint32_t lev = c.level_of[a];
     const bool fbk = kind == PRUNE_FILTERBANK;
@@ -1076,7 +1155,12 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
         ci.halo_count = 0;
         ci.count = count;
         ci.pad = 0;
+        ci.op = kOpCopy; ci.width = 0; ci.param = 0; ci.pad2 = 0;
         return ci;
+      };
+      // copy items move 8-byte words: byte-token blocks are counted in words
+      auto words = [&](uint32_t fifo, uint32_t count) -> uint32_t {
+        return fifo == kNone ? count : count * c.fifos[fifo].token_bytes / 8u;
       };
       if (kind == PRUNE_SWITCH || kind == PRUNE_POLY) {
         const float2 *hp = batch_halo(c, b, a, in_acc, i);
@@ -1092,21 +1176,36 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
         const SrcIn sin = ((const SrcIn *)A.queue)[(b.s_qbase[a] + i) % A.q_cap];
         if (sin.ptr)
           for (uint32_t k = 0; k < n_out; ++k)
-            item((const float2 *)sin.ptr, (float2 *)r.out[k].ptr, r.out[k].count);
+            item((const float2 *)sin.ptr, (float2 *)r.out[k].ptr, words(r.out[k].fifo, r.out[k].count));
       } else if (kind == PRUNE_SINK) {
         if (A.sink_out) {
           const uint64_t off = b.s_sink[a] + b.s_aux2[o];
           const uint32_t cnt = r.in[0].count;
+          const uint32_t tb = c.fifos[r.in[0].fifo].token_bytes;
+          // sink_cap and sink_pos count tokens; the output is addressed in bytes
           if (off + cnt <= A.sink_cap) {
-            item((const float2 *)r.in[0].ptr, A.sink_out + off, cnt);
+            item((const float2 *)r.in[0].ptr, (float2 *)((char *)A.sink_out + off * tb), words(r.in[0].fifo, cnt));
           } else {
             item(nullptr, A.sink_out, 0);
             atomicOr(c.err, kErrCount);
           }
         }
+      } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
+        // one item per output access: a broadcast port writes each of its
+        // FIFOs (items of one launch run unordered, so each computes)
+        for (uint32_t k = 0; k < n_out; ++k) {
+          CopyItem &ci = item((const float2 *)r.in[0].ptr, (float2 *)r.out[k].ptr, A.pix_w * A.pix_h);
+          if (kind == PRUNE_THRES) {
+            ci.src[1] = (const float2 *)r.in[1].ptr;
+            ci.n_src = 2;
+          }
+          ci.op = kind == PRUNE_GAUSS5 ? kOpGauss5 : (kind == PRUNE_THRES ? kOpThres : kOpMed5);
+          ci.width = A.pix_w;
+          ci.param = A.pix_t;
+        }
       } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
         for (uint32_t k = 0; k < n_out; ++k) {
-          CopyItem &ci = item(nullptr, (float2 *)r.out[k].ptr, r.out[k].count);
+          CopyItem &ci = item(nullptr, (float2 *)r.out[k].ptr, words(r.out[k].fifo, r.out[k].count));
           uint32_t ns = 0;
           for (int q = 0; q < kMaxIn; ++q)
             if (r.in[q].ptr) ci.src[ns++] = (const float2 *)r.in[q].ptr;

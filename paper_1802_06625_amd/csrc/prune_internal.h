@@ -118,6 +118,7 @@ struct ActorDev {
   uint32_t cfg_mode, cfg_Kmax;                     // CONFIG
   uint32_t fb;                                     // FbParamsDev index for FILTERBANK
   uint32_t fixed_mask;                             // static filter bank
+  uint32_t pix_w, pix_h, pix_t;                    // GAUSS5 / THRES / MED5
   uint32_t hist_len;                               // stream history kept by the actor
   float2 *history;                                 // [hist_len] library-owned
   uint64_t firings;                                // device firing counter

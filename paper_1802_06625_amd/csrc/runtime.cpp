@@ -90,6 +90,7 @@ struct HActor {
   std::vector<uint32_t> branches;   // filter-bank branch DRPs
   prune_config_params cfg{};
   prune_fb_params fb{};
+  prune_pixel_params pix{};
   uint32_t level = 0, comp = 0;
   uint64_t firings = 0;
   std::deque<SrcPending> src_q;
@@ -128,7 +129,7 @@ struct prune_graph {
   uint32_t n_fb = 0;
   std::vector<PortDev> h_ports;
   // structure
-  bool dag = true, has_delay = false;
+  bool dag = true, has_delay = false, has_unaligned_delay = false;
   uint32_t n_comp = 0, n_levels = 0;
   std::vector<uint32_t> comp_off, comp_actors;
   uint32_t *d_comp_off = nullptr, *d_comp_actors = nullptr, *d_iota = nullptr,
@@ -268,6 +269,13 @@ prune_status validate_actor(prune_graph *g, uint32_t aid) {
     return PRUNE_OK;
   }
   const bool dyn_kind = a.kind == PRUNE_SWITCH || a.kind == PRUNE_POLY || a.kind == PRUNE_SELECT;
+  // byte-token ports move whole 8-byte words
+  for (HPort *p : din)
+    if (p->token_bytes == 1 && (p->atr % 8 || (p->flags & PRUNE_PORT_PARAM) || p->halo))
+      return err(PRUNE_E_UNSUPPORTED, "byte-token ports carry fixed blocks of a multiple of 8 bytes");
+  for (HPort *p : outs)
+    if (p->token_bytes == 1 && (p->atr % 8 || (p->flags & PRUNE_PORT_PARAM) || p->halo))
+      return err(PRUNE_E_UNSUPPORTED, "byte-token ports carry fixed blocks of a multiple of 8 bytes");
   const bool dynamic = dyn_kind || (a.kind == PRUNE_FILTERBANK && !cps.empty());
   if (!dynamic) {
     if (!cps.empty() || !in_drp.empty() || !out_drp.empty())
@@ -333,6 +341,18 @@ prune_status validate_actor(prune_graph *g, uint32_t aid) {
         if (p->halo > PRUNE_MAX_L - 1) return fail(PRUNE_E_UNSUPPORTED, "halo beyond 63 samples");
       }
       break;
+    case PRUNE_GAUSS5:
+    case PRUNE_THRES:
+    case PRUNE_MED5: {
+      const uint32_t npix = a.pix.W * a.pix.H;
+      if (din.size() != (a.kind == PRUNE_THRES ? 2u : 1u) || outs.size() != 1)
+        return err(PRUNE_E_ARG, "pixel actors: one input (two for THRES), one output");
+      for (HPort *p : din)
+        if (p->atr != npix || p->token_bytes != 1) return err(PRUNE_E_RATE_MISMATCH, "pixel ports carry one W*H frame");
+      if (outs[0]->atr != npix || outs[0]->token_bytes != 1)
+        return err(PRUNE_E_RATE_MISMATCH, "pixel ports carry one W*H frame");
+      break;
+    }
     case PRUNE_SELECT:
       if (outs.size() != 1 || outs[0]->kind != PRUNE_SRP || in_drp.empty() || in_drp.size() != din.size())
         return err(PRUNE_E_ARG, "DRP inputs, one SRP output");
@@ -462,6 +482,7 @@ prune_status build_device(prune_graph *g) {
     d.cfg_mode = A.cfg.mode; d.cfg_Kmax = A.cfg.Kmax;
     d.fb = A.fb_index;
     d.fixed_mask = A.fb.fixed_mask;
+    d.pix_w = A.pix.W; d.pix_h = A.pix.H; d.pix_t = A.pix.threshold;
     if (A.kind == PRUNE_FILTERBANK && !A.fb.windowed) A.hist_len = fb_lmax(A.fb) - 1;
     if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_POLY) {
       for (uint32_t p : A.ports)
@@ -501,6 +522,7 @@ prune_status analyse(prune_graph *g) {
     uint32_t a = find(g->ports[F.src].actor), b = find(g->ports[F.dst].actor);
     if (a != b) par[a] = b;
     if (F.delay) g->has_delay = true;
+    if (F.delay % F.rate) g->has_unaligned_delay = true;
   }
   // levels by longest path (Kahn)
   std::vector<uint32_t> indeg(na, 0), level(na, 0);
@@ -573,6 +595,7 @@ uint32_t out_accesses(const prune_graph *g, const HActor &a) {
 
 bool is_copy_kind(uint32_t k) {
   return k == PRUNE_SWITCH || k == PRUNE_POLY || k == PRUNE_SELECT || k == PRUNE_PASSTHROUGH || k == PRUNE_SOURCE ||
+         k == PRUNE_GAUSS5 || k == PRUNE_THRES || k == PRUNE_MED5 ||
          k == PRUNE_SINK;
 }
 
@@ -924,7 +947,8 @@ void launch_masks(prune_graph *g, uint32_t B, uint64_t *copy_mask, uint64_t *gat
   *gather_mask = 0;
   for (auto &A : g->actors) {
     const uint64_t bit = 1ull << std::min<uint32_t>(A.level, 63);
-    if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_POLY || A.kind == PRUNE_SELECT || A.kind == PRUNE_PASSTHROUGH)
+    if (A.kind == PRUNE_SWITCH || A.kind == PRUNE_POLY || A.kind == PRUNE_SELECT || A.kind == PRUNE_PASSTHROUGH ||
+        A.kind == PRUNE_GAUSS5 || A.kind == PRUNE_THRES || A.kind == PRUNE_MED5)
       *copy_mask |= bit;
     if (A.kind == PRUNE_SINK && A.sink_out) *copy_mask |= bit;
     if (A.kind == PRUNE_SOURCE) {
@@ -1095,7 +1119,7 @@ prune_status prune_graph_destroy(prune_graph_t g) {
 prune_status prune_actor_create(prune_graph_t g, int kind, const void *params, size_t bytes,
                                 prune_id *actor) {
   TRY(check_graph(g, false));
-  if (!actor || kind < PRUNE_SOURCE || kind > PRUNE_POLY) return fail(PRUNE_E_ARG, "bad actor kind");
+  if (!actor || kind < PRUNE_SOURCE || kind > PRUNE_MED5) return fail(PRUNE_E_ARG, "bad actor kind");
   HActor a;
   a.kind = (uint32_t)kind;
   if (kind == PRUNE_CONFIG) {
@@ -1110,6 +1134,12 @@ prune_status prune_actor_create(prune_graph_t g, int kind, const void *params, s
       return fail(PRUNE_E_UNSUPPORTED, "at most 4 banks of 10 branches (32 in total)");
     for (uint32_t b = 0; b < a.fb.n_banks; ++b)
       if (a.fb.L[b] < 1 || a.fb.L[b] > PRUNE_MAX_L) return fail(PRUNE_E_UNSUPPORTED, "taps per branch must be 1..64");
+  } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
+    if (!params || bytes != sizeof(prune_pixel_params)) return fail(PRUNE_E_ARG, "pixel params expected");
+    a.pix = *(const prune_pixel_params *)params;
+    if (a.pix.W < 1 || a.pix.H < 1 || (uint64_t)a.pix.W * a.pix.H > 0xffffffffull ||
+        ((uint64_t)a.pix.W * a.pix.H) % 8)
+      return fail(PRUNE_E_ARG, "frame sizes must be positive with W*H a multiple of 8");
   } else if (params && bytes) {
     return fail(PRUNE_E_ARG, "this actor kind takes no parameters");
   }
@@ -1137,8 +1167,10 @@ prune_status prune_port_create(prune_graph_t g, prune_id actor, int dir, int kin
   if (kind == PRUNE_CPORT && (dir != PRUNE_IN || token_bytes != sizeof(prune_ctrl_token)))
     return fail(PRUNE_E_PORT_KIND, "a control port is an input of 8-byte control tokens");
   HActor &A = g->actors[actor];
-  if (A.kind != PRUNE_CONFIG && kind != PRUNE_CPORT && token_bytes != 8)
-    return fail(PRUNE_E_UNSUPPORTED, "data tokens are complex64 (8 bytes)");
+  const bool byte_ok = A.kind == PRUNE_SOURCE || A.kind == PRUNE_SINK || A.kind == PRUNE_PASSTHROUGH ||
+                       A.kind == PRUNE_GAUSS5 || A.kind == PRUNE_THRES || A.kind == PRUNE_MED5;
+  if (A.kind != PRUNE_CONFIG && kind != PRUNE_CPORT && token_bytes != 8 && !(token_bytes == 1 && byte_ok))
+    return fail(PRUNE_E_UNSUPPORTED, "data tokens are complex64 (8 bytes), or pixels (1 byte)");
   HPort p{};
   p.actor = actor; p.dir = (uint32_t)dir; p.kind = (uint32_t)kind; p.atr = atr;
   p.token_bytes = token_bytes; p.flags = flags; p.halo = halo;
@@ -1229,6 +1261,13 @@ prune_status prune_graph_finalize(prune_graph_t g, uint32_t C) {
   }
   TRY(build_device(g));
   g->Bcap = std::max<uint32_t>(1, std::min<uint32_t>(C, 1u << 16));
+  // A batch runs every iteration of one level before the next level, so a
+  // FIFO with an aligned delay of Q/r blocks holds Q/r + B blocks at once.
+  for (auto &F : g->fifos)
+    if (F.delay && F.delay % F.rate == 0) {
+      const uint64_t blocks = F.capacity / F.rate, pre = F.delay / F.rate;
+      g->Bcap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->Bcap, blocks > pre ? blocks - pre : 1));
+    }
   {
     uint32_t L = 0, K = 1, n = 1;
     for (auto &A : g->actors)
@@ -1315,7 +1354,7 @@ prune_status prune_source_push(prune_graph_t g, prune_id src, const void *dev_sa
       return fail(PRUNE_E_TOKEN, "frame length " + std::to_string(c) + " does not fit the source port");
     ent[f].count = c;
     ent[f].pad = 0;
-    ent[f].ptr = dev_samples ? (const char *)dev_samples + off * sizeof(float2) : nullptr;
+    ent[f].ptr = dev_samples ? (const char *)dev_samples + off * P.token_bytes : nullptr;
     off += c;
   }
   TRY(ensure_ring(g, A, sizeof(SrcIn), n));
@@ -1384,7 +1423,8 @@ prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings, p
     return PRUNE_OK;
   }
   if (mode != PRUNE_BATCHED && mode != PRUNE_BATCHED_GRAPH) return fail(PRUNE_E_ARG, "unknown mode");
-  if (!g->dag || g->has_delay) return fail(PRUNE_E_UNSUPPORTED, "batched firing needs a DAG without delays");
+  if (!g->dag || g->has_unaligned_delay)
+    return fail(PRUNE_E_UNSUPPORTED, "batched firing needs a DAG whose delays are whole blocks");
   for (auto &F : g->fifos)
     if (F.inflight || !F.mirror.empty())
       return fail(PRUNE_E_STATE, "batched firing starts at an iteration boundary");

@@ -11,11 +11,16 @@ struct SrcIn {             // one queued source frame
   const void *ptr;         // copy-in source, or null when written in place
 };
 
+// Pixel operations of the Motion Detection actors, carried by copy items.
+enum : uint32_t { kOpCopy = 0, kOpGauss5 = 1, kOpThres = 2, kOpMed5 = 3 };
+
 struct CopyItem {          // dst = halo (halo_count samples), then sum of sources
   const float2 *src[kMaxIn];
   float2 *dst;
   const float2 *halo;
-  uint32_t n_src, halo_count, count, pad;
+  uint32_t n_src, halo_count, count, pad;   // pad: POLY basis power
+  uint32_t op, width, param, pad2;          // pixel items: op, frame width, threshold;
+                                            // count = pixels (bytes), src/dst byte frames
 };
 
 struct GatherReq {         // fill dst[0..H) with the H stream samples before firing i

@@ -310,6 +310,42 @@ class UnfusedGraph:
             self.g.set_taps(f, taps[b:b + 1].reshape(1, 1, -1).contiguous())
 
 
+class MotionGraph:
+    """Motion Detection (Sec. VII-A, Fig. 7): SOURCE -> GAUSS5 -> THRES -> MED5
+    -> SINK on 8-bit W x H frames (a frame is W*H one-byte tokens).  The
+    Gauss output feeds THRES twice; the second FIFO carries a one-frame
+    delay, so THRES compares each frame with the previous one."""
+
+    def __init__(self, W, H, C_, threshold=20, device=0):
+        g = self.g = Graph(device)
+        npix = W * H
+        pp = L.PixelParams(W, H, threshold)
+        self.src = g.actor(L.SOURCE)
+        self.gauss = g.actor(L.GAUSS5, pp)
+        self.thres = g.actor(L.THRES, pp)
+        self.med = g.actor(L.MED5, pp)
+        self.snk = g.actor(L.SINK)
+        P = lambda a, d: g.port(a, d, L.SRP, npix, token_bytes=1)
+        p_src, p_gi, p_go = P(self.src, L.OUT), P(self.gauss, L.IN), P(self.gauss, L.OUT)
+        p_tc, p_tp, p_to = P(self.thres, L.IN), P(self.thres, L.IN), P(self.thres, L.OUT)
+        p_mi, p_mo, p_snk = P(self.med, L.IN), P(self.med, L.OUT), P(self.snk, L.IN)
+        self.f_in = g.connect(p_src, p_gi, npix)
+        self.f_cur = g.connect(p_go, p_tc, npix)
+        self.f_prev = g.connect(p_go, p_tp, npix, npix)
+        self.f_map = g.connect(p_to, p_mi, npix)
+        self.f_out = g.connect(p_mo, p_snk, npix)
+        g.finalize(C_, check_rules=True)
+        self.npix = npix
+        self.storage = {}
+        for f in (self.f_in, self.f_cur, self.f_prev, self.f_map, self.f_out):
+            nbytes = g.required_bytes(f)
+            t = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+            g.bind_storage(f, t)
+            self.storage[f] = t
+        self.fifo_in = self.storage[self.f_in]
+        self.fifo_out = self.storage[self.f_out]
+
+
 class RoutedGraph:
     """Per stream: SOURCE -> SWITCH -> {FILTERBANK (static, windowed),
     PASSTHROUGH} -> SELECT -> SINK, with one CONFIG (route mode)

@@ -282,3 +282,44 @@ def test_host_stream(batch, C):
     with pytest.raises(L.PruneError) as e:
         pg.g.stream_host(pg.src, pg.cfg, pg.snk, hin, wl.side[0], hout, C)   # one batch only
     assert e.value.code == L.E_ARG
+
+
+# ---------------------------------------------------------------- Motion Detection
+def _run_motion_device(frames, C, mode, trace=True):
+    from paper_1802_06625_amd.graph import MotionGraph, trace_logs
+    F, H, W = frames.shape
+    mg = MotionGraph(W, H, C)
+    g = mg.g
+    out = torch.zeros(F * H * W, dtype=torch.uint8, device="cuda")
+    g.sink_bind_output(mg.snk, out)
+    if trace:
+        g.trace_enable(64 * F + 4096)
+    g.source_push(mg.src, torch.from_numpy(frames.reshape(-1)).cuda(), np.full(F, H * W))
+    g.fire(mode)
+    g.sync()
+    res = dict(y=out.cpu().numpy().reshape(F, H, W), g=g, mg=mg)
+    if trace:
+        res["fifos"], res["ctrl"] = trace_logs(g.trace_fetch())
+    return res
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH])
+@pytest.mark.parametrize("C", [2, 3, 8])
+def test_motion_detection(mode, C):
+    """Gauss -> Thres (with the one-frame delay FIFO) -> Med on 8-bit frames:
+    motion maps and FIFO logs bit-exact against the oracle."""
+    announce(f"motion detection 40x24 mode={mode} C={C}")
+    v = synth.make_video(6, width=40, height=24)
+    y_ref, logs_ref, _, _ = og.run_motion(v, C=C)
+    dev = _run_motion_device(v, C, mode)
+    assert np.array_equal(dev["y"], y_ref)
+    compare_logs(dev, logs_ref, [])
+    compare_stats(dev["g"], logs_ref)
+
+
+def test_motion_detection_1080p():
+    announce("motion detection 1920x1080, 3 frames, batched")
+    from oracle import motion as mo
+    v = synth.make_video(3)
+    dev = _run_motion_device(v, 4, L.BATCHED, trace=False)
+    assert np.array_equal(dev["y"], mo.motion_stream(v))
