@@ -122,7 +122,8 @@ def main():
               "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup),
               "c2u": lambda: bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), None),
               "paper": lambda: bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5)),
-              "host": lambda: bench_host_stream()}[args.only]
+              "host": lambda: bench_host_stream(),
+              "motion": lambda: bench_motion(min(args.steps, 10), min(args.warmup, 5))}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     if args.copy_calib:
@@ -246,6 +247,8 @@ def main():
     if not args.only_c2:
         print("bench: unfused DPD graph", file=sys.stderr, flush=True)
         out["c2_unfused"] = bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), ms_step)
+        print("bench: motion detection", file=sys.stderr, flush=True)
+        out["motion_1080p"] = bench_motion(min(args.steps, 10), min(args.warmup, 5))
         print("bench: host source and sink over PCIe", file=sys.stderr, flush=True)
         out["c2_host_stream"] = bench_host_stream()
         print("bench: the paper's DPD shape", file=sys.stderr, flush=True)
@@ -499,6 +502,51 @@ def bench_host_stream(batch=512):
            "host_bytes_each_way": samples * 8,
            "gb_per_s_each_way": round(samples * 8 / sec / 1e9, 2)}
     del g, pg
+    torch.cuda.empty_cache()
+    return res
+
+
+# The paper's Motion Detection throughput with PRUNE on its heterogeneous
+# platforms (1080p frames/s, Table III): context for the same graph.
+PAPER_MOTION_FPS = {"AMD Radeon RX 460 (PCIe)": 772.0, "AMD Carrizo R7 iGPU": 140.0,
+                    "Intel i7-6700HQ OpenCL": 113.0}
+
+
+def bench_motion(steps, warmup, batch=64):
+    """Motion Detection (Gauss 5x5 -> Thres with a one-frame delay -> Med 5)
+    on synthetic 8-bit 1920x1080 frames, batched, frames resident in HBM."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import MotionGraph
+    W, H = 1920, 1080
+    v = synth.make_video(8)
+    mg = MotionGraph(W, H, batch + 1)
+    g = mg.g
+    npix = W * H
+    blocks = mg.fifo_in.view(-1, npix)
+    for f in range(batch):
+        blocks[f].copy_(torch.from_numpy(v[f % len(v)].reshape(-1)))
+    for _ in range(2 * (steps + warmup) + 1):
+        g.source_push(mg.src, None, np.full(batch, npix))
+    torch.cuda.synchronize()
+    g.fire(L.BATCHED_GRAPH, batch)
+    ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, batch), steps, warmup)
+    ms_stream = _time_events(lambda: g.fire(L.BATCHED, batch), steps, warmup)
+    g.sync()
+    ms = min(ms_graph, ms_stream)
+    fps = batch / (ms * 1e-3)
+    # HBM bytes per frame: source block read by Gauss, Gauss output written to
+    # two FIFOs, both read by Thres, Thres output written and read by Med,
+    # Med output written
+    bytes_per_frame = 7 * npix
+    res = {"workload": f"1920x1080 8-bit frames, batches of {batch}, Gauss 5x5 -> Thres (one-frame "
+                       "delay FIFO) -> Med 5", "frames_per_s": round(fps, 1),
+           "ms_per_batch": round(ms, 4), "mode": "batched_graph" if ms_graph <= ms_stream else "batched_stream",
+           "hbm_gbps_algorithmic": round(bytes_per_frame * fps / 1e9, 1),
+           "hbm_frac_of_8tbs": round(bytes_per_frame * fps / 8e12, 3),
+           "paper_prune_heterogeneous_fps": PAPER_MOTION_FPS}
+    del g, mg
     torch.cuda.empty_cache()
     return res
 

@@ -368,6 +368,8 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
           nitems = R[i].in[0].ptr ? out_slot : 0u;
         } else if (kind == PRUNE_SINK) {
           nitems = A.sink_out ? 1u : 0u;
+        } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
+          nitems = 1;
         } else {
           nitems = out_slot;
         }
@@ -400,7 +402,7 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
         ci.halo_count = 0;
         ci.count = count;
         ci.pad = 0;
-        ci.op = kOpCopy; ci.width = 0; ci.param = 0; ci.pad2 = 0;
+        ci.op = kOpCopy; ci.width = 0; ci.param = 0; ci.n_dst = 1;
         return ci;
       };
       auto words = [&](uint32_t fifo, uint32_t count) -> uint32_t {
@@ -424,16 +426,15 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
         } else if (kind == PRUNE_SINK) {
           item((const float2 *)R[i].in[0].ptr, sink_dst, words(R[i].in[0].fifo, R[i].in[0].count));
         } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
-          for (uint32_t k = 0; k < out_slot; ++k) {   // one item per output access (broadcast)
-            CopyItem &ci = item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[k].ptr, A.pix_w * A.pix_h);
-            if (kind == PRUNE_THRES) {
-              ci.src[1] = (const float2 *)R[i].in[1].ptr;
-              ci.n_src = 2;
-            }
-            ci.op = kind == PRUNE_GAUSS5 ? kOpGauss5 : (kind == PRUNE_THRES ? kOpThres : kOpMed5);
-            ci.width = A.pix_w;
-            ci.param = A.pix_t;
-          }
+          CopyItem &ci = item((const float2 *)R[i].in[0].ptr, (float2 *)R[i].out[0].ptr, A.pix_w * A.pix_h);
+          ci.src[1] = kind == PRUNE_THRES ? (const float2 *)R[i].in[1].ptr : nullptr;
+          ci.n_src = kind == PRUNE_THRES ? 2 : 1;
+          for (uint32_t k = 1; k < out_slot && k + 1 < (uint32_t)kMaxIn; ++k)
+            ci.src[k + 1] = (const float2 *)R[i].out[k].ptr;
+          ci.n_dst = out_slot;
+          ci.op = kind == PRUNE_GAUSS5 ? kOpGauss5 : (kind == PRUNE_THRES ? kOpThres : kOpMed5);
+          ci.width = A.pix_w;
+          ci.param = A.pix_t;
         } else {
           // SELECT sums its active inputs; PASSTHROUGH copies its input.
           for (uint32_t k = 0; k < out_slot; ++k) {
@@ -517,6 +518,66 @@ __device__ inline uint32_t pixel_op(uint32_t op, const uint8_t *a, const uint8_t
   return median5(row[x], row[x - W], row[x + W], row[max(x - 1, 0)], row[min(x + 1, W - 1)]);
 }
 
+__device__ inline uint32_t byte_of(uint32_t w, int j) { return (w >> (8 * j)) & 0xffu; }
+
+// Pixels k0..k0+3 (k0 a multiple of 4) packed little-endian.  Interior
+// groups read aligned words; groups next to an edge column or in a copied
+// border row take the per-pixel path.
+__device__ inline uint32_t pixel4(uint32_t op, const uint8_t *a, const uint8_t *b, uint32_t k0,
+                                  int W, int H, uint32_t T) {
+  const int y = (int)(k0 / (uint32_t)W), x0 = (int)(k0 - (uint32_t)y * W);
+  if (op == kOpThres) {
+    const uint32_t wa = *(const uint32_t *)(a + k0), wb = *(const uint32_t *)(b + k0);
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = (int)byte_of(wa, j) - (int)byte_of(wb, j);
+      v |= (uint32_t)(d > (int)T || -d > (int)T) * (255u << (8 * j));
+    }
+    return v;
+  }
+  if (op == kOpGauss5 && y >= 2 && y <= H - 3 && x0 >= 4 && x0 + 8 <= W) {
+    // columns x0-4 .. x0+7 of rows y-2 .. y+2 in three words each
+    const uint32_t w[5] = {1, 4, 6, 4, 1};
+    uint32_t acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int dy = 0; dy < 5; ++dy) {
+      const uint32_t *r = (const uint32_t *)(a + (size_t)(y + dy - 2) * W + x0 - 4);
+      const uint32_t w0 = r[0], w1 = r[1], w2 = r[2];
+      uint32_t p[8];   // columns x0-2 .. x0+5
+      p[0] = byte_of(w0, 2); p[1] = byte_of(w0, 3);
+      p[2] = byte_of(w1, 0); p[3] = byte_of(w1, 1); p[4] = byte_of(w1, 2); p[5] = byte_of(w1, 3);
+      p[6] = byte_of(w2, 0); p[7] = byte_of(w2, 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t h = p[j] + 4 * p[j + 1] + 6 * p[j + 2] + 4 * p[j + 3] + p[j + 4];
+        acc[j] += w[dy] * h;
+      }
+    }
+    return ((acc[0] + 128u) >> 8) | (((acc[1] + 128u) >> 8) << 8) | (((acc[2] + 128u) >> 8) << 16) |
+           (((acc[3] + 128u) >> 8) << 24);
+  }
+  if (op == kOpMed5 && y >= 1 && y <= H - 2 && x0 >= 4 && x0 + 8 <= W) {
+    const uint8_t *row = a + (size_t)y * W + x0;
+    const uint32_t wl = *(const uint32_t *)(row - 4), wc = *(const uint32_t *)row, wr = *(const uint32_t *)(row + 4);
+    const uint32_t wu = *(const uint32_t *)(row - W), wd = *(const uint32_t *)(row + W);
+    uint32_t p[6];   // columns x0-1 .. x0+4 of row y
+    p[0] = byte_of(wl, 3);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) p[j + 1] = byte_of(wc, j);
+    p[5] = byte_of(wr, 0);
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v |= median5(p[j + 1], byte_of(wu, j), byte_of(wd, j), p[j], p[j + 2]) << (8 * j);
+    return v;
+  }
+  uint32_t v = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v |= pixel_op(op, a, b, k0 + j, W, H, T) << (8 * j);
+  return v;
+}
+
 // Items with a nonzero power (POLY outputs) store |v|^power * v; pixel
 // items (op != kOpCopy) run a Motion Detection actor over a byte frame.  The
 // item is staged in LDS so that its source list is indexed there rather
@@ -537,10 +598,15 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
     if (s_ci.op != kOpCopy) {
       const uint8_t *a = (const uint8_t *)s_ci.src[0];
       const uint8_t *b = (const uint8_t *)s_ci.src[1];
-      uint8_t *o = (uint8_t *)s_ci.dst;
       const int W = (int)s_ci.width, H = (int)(s_ci.count / s_ci.width);
-      const uint32_t op = s_ci.op, T = s_ci.param;
-      for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) o[k] = (uint8_t)pixel_op(op, a, b, k, W, H, T);
+      const uint32_t op = s_ci.op, T = s_ci.param, nd = s_ci.n_dst;
+      // four consecutive pixels per thread (W and the frame bases are
+      // multiples of 4, so a group never leaves its row or splits a word)
+      for (uint32_t k = lo + 4 * threadIdx.x; k < hi; k += 4 * blockDim.x) {
+        const uint32_t v = pixel4(op, a, b, k, W, H, T);
+        *(uint32_t *)((uint8_t *)s_ci.dst + k) = v;
+        for (uint32_t q = 1; q < nd; ++q) *(uint32_t *)((uint8_t *)s_ci.src[q + 1] + k) = v;
+      }
       continue;
     }
     float2 *dst = s_ci.dst;
@@ -758,9 +824,10 @@ __global__ __launch_bounds__(256) void k_batch_decode(CtrlArgs c, BatchArgs b) {
         aux = src_ptr ? n_out : 0;
       } else if (kind == PRUNE_SINK) {
         aux = A.sink_out ? 1 : 0;
-      } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH || kind == PRUNE_GAUSS5 ||
-                 kind == PRUNE_THRES || kind == PRUNE_MED5) {
+      } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
         aux = n_out;
+      } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
+        aux = 1;
       }
     }
     const size_t o = (size_t)a * Bc + i;
@@ -1155,7 +1222,7 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
         ci.halo_count = 0;
         ci.count = count;
         ci.pad = 0;
-        ci.op = kOpCopy; ci.width = 0; ci.param = 0; ci.pad2 = 0;
+        ci.op = kOpCopy; ci.width = 0; ci.param = 0; ci.n_dst = 1;
         return ci;
       };
       // copy items move 8-byte words: byte-token blocks are counted in words
@@ -1191,18 +1258,16 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
           }
         }
       } else if (kind == PRUNE_GAUSS5 || kind == PRUNE_THRES || kind == PRUNE_MED5) {
-        // one item per output access: a broadcast port writes each of its
-        // FIFOs (items of one launch run unordered, so each computes)
-        for (uint32_t k = 0; k < n_out; ++k) {
-          CopyItem &ci = item((const float2 *)r.in[0].ptr, (float2 *)r.out[k].ptr, A.pix_w * A.pix_h);
-          if (kind == PRUNE_THRES) {
-            ci.src[1] = (const float2 *)r.in[1].ptr;
-            ci.n_src = 2;
-          }
-          ci.op = kind == PRUNE_GAUSS5 ? kOpGauss5 : (kind == PRUNE_THRES ? kOpThres : kOpMed5);
-          ci.width = A.pix_w;
-          ci.param = A.pix_t;
-        }
+        // one item computes the frame once and stores it to every FIFO of the
+        // (broadcast) output port: dst, then src[2..]
+        CopyItem &ci = item((const float2 *)r.in[0].ptr, (float2 *)r.out[0].ptr, A.pix_w * A.pix_h);
+        ci.src[1] = kind == PRUNE_THRES ? (const float2 *)r.in[1].ptr : nullptr;
+        ci.n_src = kind == PRUNE_THRES ? 2 : 1;
+        for (uint32_t k = 1; k < n_out && k + 1 < (uint32_t)kMaxIn; ++k) ci.src[k + 1] = (const float2 *)r.out[k].ptr;
+        ci.n_dst = n_out;
+        ci.op = kind == PRUNE_GAUSS5 ? kOpGauss5 : (kind == PRUNE_THRES ? kOpThres : kOpMed5);
+        ci.width = A.pix_w;
+        ci.param = A.pix_t;
       } else if (kind == PRUNE_SELECT || kind == PRUNE_PASSTHROUGH) {
         for (uint32_t k = 0; k < n_out; ++k) {
           CopyItem &ci = item(nullptr, (float2 *)r.out[k].ptr, words(r.out[k].fifo, r.out[k].count));

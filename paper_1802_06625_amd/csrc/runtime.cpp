@@ -1140,6 +1140,7 @@ prune_status prune_actor_create(prune_graph_t g, int kind, const void *params, s
     if (a.pix.W < 1 || a.pix.H < 1 || (uint64_t)a.pix.W * a.pix.H > 0xffffffffull ||
         ((uint64_t)a.pix.W * a.pix.H) % 8)
       return fail(PRUNE_E_ARG, "frame sizes must be positive with W*H a multiple of 8");
+    if (a.pix.W % 4) return fail(PRUNE_E_UNSUPPORTED, "frame width must be a multiple of 4");
   } else if (params && bytes) {
     return fail(PRUNE_E_ARG, "this actor kind takes no parameters");
   }

@@ -19,8 +19,9 @@ struct CopyItem {          // dst = halo (halo_count samples), then sum of sourc
   float2 *dst;
   const float2 *halo;
   uint32_t n_src, halo_count, count, pad;   // pad: POLY basis power
-  uint32_t op, width, param, pad2;          // pixel items: op, frame width, threshold;
-                                            // count = pixels (bytes), src/dst byte frames
+  uint32_t op, width, param, n_dst;         // pixel items: op, frame width, threshold and
+                                            // destinations (dst, then src[2..]); count =
+                                            // pixels; src[0..1] and the outputs are byte frames
 };
 
 struct GatherReq {         // fill dst[0..H) with the H stream samples before firing i
