@@ -555,6 +555,15 @@ prune_status prune_autotune_bwd(uint32_t L, uint32_t K, uint32_t n, int *variant
 prune_status prune_timing_enable(int on);
 prune_status prune_last_fb_kernel_ms(float *ms, uint32_t *launches);
 
+/* Batched firing without hipGraph (PRUNE_BATCHED): with on != 0 (the
+ * default) a graph's bookkeeping kernels (firing decode, index scans,
+ * firing records and work lists) run on a stream the graph owns, ordered by
+ * events, so that batch i+1's bookkeeping overlaps batch i's data kernels on
+ * the caller's stream.  Two sets of per-batch buffers alternate.  Results
+ * are identical either way; the caller's stream still completes after all
+ * of a fire call's work.  Process-wide; takes effect at the next batch. */
+prune_status prune_set_batch_pipeline(int on);
+
 /* ---- host evaluation of the integer rules -------------------------------- */
 /* The kernels' integer rules compiled for the host from the same source:
  * Eq. 2 capacity (tokens), the first slots of writes and reads 0..n-1 of a

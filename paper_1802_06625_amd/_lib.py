@@ -124,6 +124,7 @@ SIGNATURES = [
     ("prune_bwd_variant_name", C.c_char_p, [C.c_int]),
     ("prune_autotune_bwd", _ST, [C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int)]),
     ("prune_timing_enable", _ST, [C.c_int]),
+    ("prune_set_batch_pipeline", _ST, [C.c_int]),
     ("prune_last_fb_kernel_ms", _ST, [C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
     ("prune_rule_capacity", _ST, [C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64)]),
     ("prune_rule_slots", _ST, [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -29,6 +30,7 @@ thread_local std::string g_last_error;
 thread_local float g_fb_ms = 0.f;
 thread_local uint32_t g_fb_launches = 0;
 thread_local bool g_timing = false;
+std::atomic<bool> g_pipeline{true};   // batched firing: bookkeeping on a side stream
 thread_local std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 int g_variant_forced = 0;
 }  // namespace
@@ -170,11 +172,28 @@ struct prune_graph {
   int ncu = 256;
   int fb_grid = 768;
   std::vector<void *> owned;
+  // Per-batch buffers in two sets.  In stream mode the bookkeeping of batch
+  // i (decode, scan, emit) runs on a side stream into set i%2 while the data
+  // kernels of batch i-1 still read the other set on the caller's stream.
+  struct BatchSet {
+    FiringRec *recs; uint32_t *wrote; FbFrameDesc *desc; WorkItem *items; CopyItem *copy;
+    float2 *halo_scratch; uint32_t *ctr; GatherReq *gather;
+  };
+  BatchSet sets[2]{};
+  uint32_t parity = 0;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_emit[2]{}, ev_done[2]{}, ev_sync = nullptr;
+  bool done_valid[2]{};
+  bool need_sync = true;    // the caller's stream has work the side stream must wait for
 
   ~prune_graph();
 };
 
 prune_graph::~prune_graph() {
+  if (side_stream) hipStreamSynchronize(side_stream);
+  for (hipEvent_t e : {ev_emit[0], ev_emit[1], ev_done[0], ev_done[1], ev_sync})
+    if (e) hipEventDestroy(e);
+  if (side_stream) hipStreamDestroy(side_stream);
   for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
   for (auto &kv : graph_defs) hipGraphDestroy(kv.second);
   if (capture_stream) hipStreamDestroy(capture_stream);
@@ -661,6 +680,18 @@ prune_status alloc_scratch(prune_graph *g) {
   TRY(upload(g, &g->d_halo_off, halo_off));
   TRY(dalloc(g, &g->d_ctr, 4 * nl));
   TRY(dalloc(g, &g->d_gather, go));
+  g->sets[0] = {g->d_recs, g->d_wrote, g->d_desc, g->d_items, g->d_copy, g->d_halo_scratch, g->d_ctr, g->d_gather};
+  {
+    prune_graph::BatchSet &S = g->sets[1];
+    TRY(dalloc(g, &S.recs, (size_t)na * Bc));
+    TRY(dalloc(g, &S.wrote, (size_t)g->fifos.size() * Bc));
+    TRY(dalloc(g, &S.desc, ndesc));
+    TRY(dalloc(g, &S.items, fo));
+    TRY(dalloc(g, &S.copy, co));
+    TRY(dalloc(g, &S.halo_scratch, nhalo));
+    TRY(dalloc(g, &S.ctr, 4 * nl));
+    TRY(dalloc(g, &S.gather, go));
+  }
   TRY(upload(g, &g->d_gather_off, g->gather_off));
   TRY(dalloc(g, &g->d_err, 1));
   TRY(upload(g, &g->d_post_actors, g->post_actors));
@@ -966,10 +997,18 @@ void launch_masks(prune_graph *g, uint32_t B, uint64_t *copy_mask, uint64_t *gat
   }
 }
 
+// Point the graph's per-batch buffers at set p (kernels take the pointers by
+// value at launch).
+void use_set(prune_graph *g, uint32_t p) {
+  const prune_graph::BatchSet &S = g->sets[p];
+  g->d_recs = S.recs; g->d_wrote = S.wrote; g->d_desc = S.desc; g->d_items = S.items;
+  g->d_copy = S.copy; g->d_halo_scratch = S.halo_scratch; g->d_ctr = S.ctr; g->d_gather = S.gather;
+}
+
 prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph) {
   uint64_t cmask, gmask;
   launch_masks(g, B, &cmask, &gmask);
-  auto enqueue = [&](hipStream_t st) {
+  auto bookkeeping = [&](hipStream_t st) {
     CtrlArgs c = make_args(g, B);
     if (g->fast_batch) {
       c.clear_n = 4 * g->n_levels;
@@ -978,6 +1017,9 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
       launch_clear(g->d_ctr, 4 * g->n_levels, st);
       launch_control(c, g->n_comp, st);
     }
+  };
+  auto data = [&](hipStream_t st) {
+    CtrlArgs c = make_args(g, B);
     for (uint32_t l = 0; l < g->n_levels; ++l) {
       const uint64_t bit = 1ull << std::min<uint32_t>(l, 63);
       if ((gmask & bit) && g->gather_cap[l])
@@ -989,6 +1031,37 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
     }
     launch_post(c, g->d_post_actors, (uint32_t)g->post_actors.size(), st);
   };
+  auto enqueue = [&](hipStream_t st) {
+    bookkeeping(st);
+    data(st);
+  };
+  if (!use_graph && g->fast_batch && g->side_stream && g_pipeline) {
+    // pipelined: bookkeeping on the side stream into set p, data kernels on
+    // the caller's stream once it is done; set p is reused only after the
+    // data kernels of the batch that last used it
+    const uint32_t p = g->parity;
+    use_set(g, p);
+    hipStream_t b = g->side_stream;
+    if (g->need_sync) {
+      HIPCHECK(hipEventRecord(g->ev_sync, s));
+      HIPCHECK(hipStreamWaitEvent(b, g->ev_sync, 0));
+      g->need_sync = false;
+    } else if (g->done_valid[p]) {
+      HIPCHECK(hipStreamWaitEvent(b, g->ev_done[p], 0));
+    }
+    bookkeeping(b);
+    HIPCHECK(hipEventRecord(g->ev_emit[p], b));
+    HIPCHECK(hipStreamWaitEvent(s, g->ev_emit[p], 0));
+    data(s);
+    HIPCHECK(hipEventRecord(g->ev_done[p], s));
+    g->done_valid[p] = true;
+    g->parity ^= 1u;
+    HIPCHECK(hipGetLastError());
+    return PRUNE_OK;
+  }
+  // single-stream forms use set 0; the next pipelined batch waits for them
+  use_set(g, 0);
+  g->need_sync = true;
   if (!use_graph) {
     enqueue(s);
     HIPCHECK(hipGetLastError());
@@ -1282,6 +1355,11 @@ prune_status prune_graph_finalize(prune_graph_t g, uint32_t C) {
   g->tile = (uint32_t)fb_variant_tile(g->variant);
   g->fb_grid = g->ncu * 3;
   TRY(alloc_scratch(g));
+  if (g->fast_batch) {
+    HIPCHECK(hipStreamCreateWithFlags(&g->side_stream, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&g->ev_emit[0], &g->ev_emit[1], &g->ev_done[0], &g->ev_done[1], &g->ev_sync})
+      HIPCHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
   g->finalized = true;
   return PRUNE_OK;
 }
@@ -1395,6 +1473,10 @@ prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings, p
     if (!g->fifos[f].storage) return fail(PRUNE_E_STATE, "fifo " + std::to_string(f) + " has no storage");
   uint64_t done = 0;
   if (mode == PRUNE_PER_FIRING) {
+    // per-firing kernels update FIFO counters on the caller's stream: the
+    // next pipelined batch's bookkeeping waits for them
+    use_set(g, 0);
+    g->need_sync = true;
     for (;;) {
       bool any = false;
       for (uint32_t a = 0; a < g->actors.size(); ++a) {
@@ -1659,6 +1741,11 @@ prune_status prune_set_fb_variant(int v) {
 
 const char *prune_fb_variant_name(int v) { return fb_variant_name(v); }
 int prune_fb_variant_count(void) { return fb_variant_count(); }
+
+prune_status prune_set_batch_pipeline(int on) {
+  g_pipeline = on != 0;
+  return PRUNE_OK;
+}
 
 prune_status prune_timing_enable(int on) {
   g_timing = on != 0;

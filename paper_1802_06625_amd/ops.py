@@ -168,6 +168,11 @@ def autotuned_bwd_variant(L_, K, n):
     return v.value
 
 
+def set_batch_pipeline(on=True):
+    """Bookkeeping of the next batch on a side stream (default on)."""
+    call("prune_set_batch_pipeline", int(on))
+
+
 def timing_enable(on=True):
     call("prune_timing_enable", int(on))
 

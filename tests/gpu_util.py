@@ -22,7 +22,7 @@ def announce(msg):
 
 
 def run_plain_device(wl, C, mode, s=0, atr=None, param=None, inplace=False, trace=True,
-                     batches=None, cfg_mode=L.CONFIG_PREFIX):
+                     batches=None, cfg_mode=L.CONFIG_PREFIX, src_rounds=False):
     n = wl.side[s, :, 1].astype(np.int64)
     if param is None:
         param = bool(np.any(n != n[0]))
@@ -47,7 +47,7 @@ def run_plain_device(wl, C, mode, s=0, atr=None, param=None, inplace=False, trac
             pg.fifo_in[k:k + n[f]] = x[off[f]:off[f + 1]]
         torch.cuda.synchronize()
         g.source_push(pg.src, None, n)
-    else:
+    elif not src_rounds:
         g.source_push(pg.src, x, n)
     side = wl.side[s]
     if batches is None:
@@ -55,10 +55,17 @@ def run_plain_device(wl, C, mode, s=0, atr=None, param=None, inplace=False, trac
         g.fire(mode)
     else:
         # push and fire in several rounds
+        # push and fire in several rounds; a list of modes gives each round's
+        # (src_rounds: source frames are pushed per round too, so that a
+        # per-firing round ends at an iteration boundary)
+        modes = list(mode) if isinstance(mode, (list, tuple)) else [mode] * batches
         edges = np.linspace(0, len(n), batches + 1).astype(int)
-        for a, b in zip(edges[:-1], edges[1:]):
+        off = np.concatenate([[0], np.cumsum(n)])
+        for a, b, m in zip(edges[:-1], edges[1:], modes):
+            if src_rounds:
+                g.source_push(pg.src, x[off[a]:off[b]], n[a:b])
             g.config_push(pg.cfg, side[a:b])
-            g.fire(mode)
+            g.fire(m)
     g.sync()
     y = out.cpu().numpy()
     res = dict(y=y, pg=pg, g=g)

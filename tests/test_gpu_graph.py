@@ -61,6 +61,36 @@ def test_batched_equals_per_firing_logs():
     assert rel_l2(b["y"], a["y"]) <= 1e-6
 
 
+def test_batch_pipeline_on_off_identical():
+    """Bookkeeping on the side stream or on the caller's stream: the same
+    bits (sink output and every log), over many batches (C=3)."""
+    announce("batch pipeline on/off (C2-scaled, C=3)")
+    from paper_1802_06625_amd import ops
+    wl = synth.scaled("C2")
+    try:
+        ops.set_batch_pipeline(False)
+        a = run_plain_device(wl, 3, L.BATCHED)
+    finally:
+        ops.set_batch_pipeline(True)
+    b = run_plain_device(wl, 3, L.BATCHED)
+    assert np.array_equal(a["y"], b["y"])
+    assert a["fifos"] == b["fifos"]
+    assert a["ctrl"] == b["ctrl"]
+
+
+def test_modes_mixed_across_rounds():
+    """Rounds fired in alternating modes share one stream state: pipelined
+    batches after per-firing and hipGraph rounds wait for them."""
+    announce("mixed modes across rounds (C2-scaled, C=4)")
+    wl = synth.scaled("C2")
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=4)
+    modes = [L.BATCHED, L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH, L.BATCHED, L.BATCHED]
+    dev = run_plain_device(wl, 4, modes, batches=len(modes), src_rounds=True)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+    compare_stats(dev["g"], logs_ref)
+
+
 def test_inplace_source_frames():
     announce("in-place source frames (C2-scaled)")
     wl = synth.scaled("C2")
