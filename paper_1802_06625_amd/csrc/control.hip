@@ -473,109 +473,194 @@ __global__ __launch_bounds__(1024) void k_control(CtrlArgs c) {
 // the level, y over chunks of kCopyChunk samples.
 constexpr uint32_t kCopyChunk = 4096;
 
-// Median of five values: a sorting network on the low three after
-// discarding the two extremes of pairs.
-__device__ inline uint32_t median5(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
-  // order (a, b) and (c, d), drop the smaller of the two minima and the
-  // larger of the two maxima: the median of five is the median of the rest
-  if (a > b) { const uint32_t t = a; a = b; b = t; }
-  if (c > d) { const uint32_t t = c; c = d; d = t; }
-  if (a < c) { a = e; if (a > b) { const uint32_t t = a; a = b; b = t; } }
-  else       { c = e; if (c > d) { const uint32_t t = c; c = d; d = t; } }
-  if (a < c) return b < c ? b : c;
-  return d < a ? d : a;
+// ---- Motion Detection pixel actors on byte frames -------------------------
+// Four pixels (one 32-bit word) per thread and row.  Two-lane arithmetic:
+// bytes 0 and 2 of a word go to the 16-bit lanes of one register (even
+// pixels), bytes 1 and 3 to another (odd pixels); sums that stay below 2^16
+// per lane need no carry handling.
+__device__ inline uint32_t lanes_even(uint32_t w) { return __builtin_amdgcn_perm(0u, w, 0x0c020c00u); }
+__device__ inline uint32_t lanes_odd(uint32_t w) { return __builtin_amdgcn_perm(0u, w, 0x0c030c01u); }
+// [hi lane of lo, lo lane of hi]: the lane pair one position to the left of hi
+__device__ inline uint32_t lanes_shift(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbit(hi, lo, 16u); }
+// bytes 0 of the even and odd lane registers back into one word
+__device__ inline uint32_t lanes_pack(uint32_t ev, uint32_t od) { return __builtin_amdgcn_perm(od, ev, 0x06020400u); }
+// the word's first (last) pixel in all four bytes: the columns beyond the
+// left (right) frame edge repeat the edge pixel
+__device__ inline uint32_t rep_first(uint32_t w) { return __builtin_amdgcn_perm(0u, w, 0x00000000u); }
+__device__ inline uint32_t rep_last(uint32_t w) { return __builtin_amdgcn_perm(0u, w, 0x03030303u); }
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t lanes_min(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+__device__ inline uint32_t lanes_max(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
 }
 
-// One pixel of a Motion Detection actor.  src/dst are byte frames of W
-// columns and H rows; k = y*W + x.
-__device__ inline uint32_t pixel_op(uint32_t op, const uint8_t *a, const uint8_t *b, uint32_t k,
-                                    int W, int H, uint32_t T) {
-  const int y = (int)(k / (uint32_t)W), x = (int)(k - (uint32_t)y * W);
-  if (op == kOpThres) {
-    const int d = (int)a[k] - (int)b[k];
-    return (uint32_t)(d > (int)T || -d > (int)T) * 255u;
-  }
-  if (op == kOpGauss5) {
-    if (y < 2 || y > H - 3) return a[k];
-    const uint32_t w[5] = {1, 4, 6, 4, 1};
-    int xs[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) xs[q] = min(max(x + q - 2, 0), W - 1);
-    uint32_t acc = 0;
-#pragma unroll
-    for (int dy = 0; dy < 5; ++dy) {
-      const uint8_t *row = a + (size_t)(y + dy - 2) * W;
-      uint32_t h = 0;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) h += w[q] * row[xs[q]];
-      acc += w[dy] * h;
-    }
-    return (acc + 128u) >> 8;
-  }
-  // kOpMed5
-  if (y < 1 || y > H - 2) return a[k];
-  const uint8_t *row = a + (size_t)y * W;
-  return median5(row[x], row[x - W], row[x + W], row[max(x - 1, 0)], row[min(x + 1, W - 1)]);
+// Median of five per lane: of the pairs (a, b) and (c, d), the smaller
+// minimum and the larger maximum lie on either side of the median, so the
+// median of five is the median of the larger minimum, the smaller maximum
+// and e.
+__device__ inline uint32_t lanes_median5(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
+  const uint32_t x = lanes_max(lanes_min(a, b), lanes_min(c, d));
+  const uint32_t y = lanes_min(lanes_max(a, b), lanes_max(c, d));
+  return lanes_max(lanes_min(x, y), lanes_min(lanes_max(x, y), e));
 }
 
-__device__ inline uint32_t byte_of(uint32_t w, int j) { return (w >> (8 * j)) & 0xffu; }
+// Vertical binomial [1 4 6 4 1] of one lane register over five rows:
+// r0 + r4 + 4 (r1 + r2 + r3) + 2 r2, at most 16 * 255 per lane.
+__device__ inline uint32_t lanes_binom(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t r4) {
+  return r0 + r4 + (r2 << 1) + ((r1 + r2 + r3) << 2);
+}
 
-// Pixels k0..k0+3 (k0 a multiple of 4) packed little-endian.  Interior
-// groups read aligned words; groups next to an edge column or in a copied
-// border row take the per-pixel path.
-__device__ inline uint32_t pixel4(uint32_t op, const uint8_t *a, const uint8_t *b, uint32_t k0,
-                                  int W, int H, uint32_t T) {
-  const int y = (int)(k0 / (uint32_t)W), x0 = (int)(k0 - (uint32_t)y * W);
-  if (op == kOpThres) {
-    const uint32_t wa = *(const uint32_t *)(a + k0), wb = *(const uint32_t *)(b + k0);
-    uint32_t v = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int d = (int)byte_of(wa, j) - (int)byte_of(wb, j);
-      v |= (uint32_t)(d > (int)T || -d > (int)T) * (255u << (8 * j));
-    }
-    return v;
+// Where a pixel item's word goes: the item's destination and, for a
+// broadcast output, the further destinations listed after the two sources.
+struct PixelDst {
+  uint8_t *d0, *d1;
+  const CopyItem *ci;   // LDS copy, for destinations beyond the second
+  uint32_t nd;
+  __device__ void store(size_t k, uint32_t v) const {
+    *(uint32_t *)(d0 + k) = v;
+    if (nd > 1) *(uint32_t *)(d1 + k) = v;
+    for (uint32_t q = 2; q < nd; ++q) *(uint32_t *)((uint8_t *)ci->src[q + 1] + k) = v;
   }
-  if (op == kOpGauss5 && y >= 2 && y <= H - 3 && x0 >= 4 && x0 + 8 <= W) {
-    // columns x0-4 .. x0+7 of rows y-2 .. y+2 in three words each
-    const uint32_t w[5] = {1, 4, 6, 4, 1};
-    uint32_t acc[4] = {0, 0, 0, 0};
+};
+
+// A thread takes its rows in steps of kPixRows output rows and issues every
+// load of a step before using any of them, so that each wave keeps many
+// loads in flight.  Rows outside the frame are clamped (in bounds; such rows
+// only feed copied border rows).
+constexpr int kPixRows = 4;
+// Rows of a pixel frame per chunk of the grid's y dimension.
+constexpr uint32_t kPixChunkRows = 16;
+
+// Gauss 5x5 (binomial weights, (sum + 128) >> 8) of rows [ya, yb) at word
+// column c.  Rows 0, 1, H-2 and H-1 are copied.  A step loads rows y0-2 ..
+// y0+5, three words each (columns x-4 .. x+7 for x = 4c).  Vertical pass
+// first, then the horizontal one on lane pairs shifted by one pixel
+// position; every lane stays below 16 * 16 * 255 + 128 < 2^16.
+__device__ void gauss_rows(const uint8_t *a, const PixelDst &out, int W, int H, uint32_t c, uint32_t G,
+                           int ya, int yb) {
+  const uint32_t xc = 4 * c, xl = c ? xc - 4 : xc, xr = c + 1 < G ? xc + 4 : xc;
+  const bool at_left = c == 0, at_right = c + 1 == G;
+  for (int y0 = ya; y0 < yb; y0 += kPixRows) {
+    uint32_t wl[kPixRows + 4], wc[kPixRows + 4], wr[kPixRows + 4];
 #pragma unroll
-    for (int dy = 0; dy < 5; ++dy) {
-      const uint32_t *r = (const uint32_t *)(a + (size_t)(y + dy - 2) * W + x0 - 4);
-      const uint32_t w0 = r[0], w1 = r[1], w2 = r[2];
-      uint32_t p[8];   // columns x0-2 .. x0+5
-      p[0] = byte_of(w0, 2); p[1] = byte_of(w0, 3);
-      p[2] = byte_of(w1, 0); p[3] = byte_of(w1, 1); p[4] = byte_of(w1, 2); p[5] = byte_of(w1, 3);
-      p[6] = byte_of(w2, 0); p[7] = byte_of(w2, 1);
+    for (int i = 0; i < kPixRows + 4; ++i) {
+      const uint8_t *row = a + (size_t)min(max(y0 - 2 + i, 0), H - 1) * W;
+      wl[i] = *(const uint32_t *)(row + xl);
+      wc[i] = *(const uint32_t *)(row + xc);
+      wr[i] = *(const uint32_t *)(row + xr);
+    }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t h = p[j] + 4 * p[j + 1] + 6 * p[j + 2] + 4 * p[j + 3] + p[j + 4];
-        acc[j] += w[dy] * h;
+    for (int i = 0; i < kPixRows + 4; ++i) {
+      if (at_left) wl[i] = rep_first(wc[i]);
+      if (at_right) wr[i] = rep_last(wc[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < kPixRows; ++j) {
+      const int y = y0 + j;
+      if (y >= yb) break;
+      uint32_t v = wc[j + 2];   // border rows are copied
+      if (y >= 2 && y <= H - 3) {
+        // vertical sums: [v(x-4), v(x-2)], [v(x-3), v(x-1)], [v(x), v(x+2)], ...
+        const uint32_t ve0 = lanes_binom(lanes_even(wl[j]), lanes_even(wl[j + 1]), lanes_even(wl[j + 2]),
+                                         lanes_even(wl[j + 3]), lanes_even(wl[j + 4]));
+        const uint32_t vo0 = lanes_binom(lanes_odd(wl[j]), lanes_odd(wl[j + 1]), lanes_odd(wl[j + 2]),
+                                         lanes_odd(wl[j + 3]), lanes_odd(wl[j + 4]));
+        const uint32_t ve1 = lanes_binom(lanes_even(wc[j]), lanes_even(wc[j + 1]), lanes_even(wc[j + 2]),
+                                         lanes_even(wc[j + 3]), lanes_even(wc[j + 4]));
+        const uint32_t vo1 = lanes_binom(lanes_odd(wc[j]), lanes_odd(wc[j + 1]), lanes_odd(wc[j + 2]),
+                                         lanes_odd(wc[j + 3]), lanes_odd(wc[j + 4]));
+        const uint32_t ve2 = lanes_binom(lanes_even(wr[j]), lanes_even(wr[j + 1]), lanes_even(wr[j + 2]),
+                                         lanes_even(wr[j + 3]), lanes_even(wr[j + 4]));
+        const uint32_t vo2 = lanes_binom(lanes_odd(wr[j]), lanes_odd(wr[j + 1]), lanes_odd(wr[j + 2]),
+                                         lanes_odd(wr[j + 3]), lanes_odd(wr[j + 4]));
+        // even outputs (x, x+2) and odd outputs (x+1, x+3):
+        // h(x) = v(x-2) + v(x+2) + 2 v(x) + 4 (v(x-1) + v(x) + v(x+1))
+        const uint32_t e_m2 = lanes_shift(ve1, ve0);   // v(x-2) at the even pixels
+        const uint32_t e_p2 = lanes_shift(ve2, ve1);   // v(x+2) at the even pixels = v(x+1) at the odd ones
+        const uint32_t o_m1 = lanes_shift(vo1, vo0);   // v(x-1) at the even pixels = v(x-2) at the odd ones
+        const uint32_t o_p2 = lanes_shift(vo2, vo1);   // v(x+2) at the odd pixels
+        const uint32_t he = e_m2 + e_p2 + (ve1 << 1) + ((o_m1 + ve1 + vo1) << 2) + 0x00800080u;
+        const uint32_t ho = o_m1 + o_p2 + (vo1 << 1) + ((ve1 + vo1 + e_p2) << 2) + 0x00800080u;
+        v = __builtin_amdgcn_perm(ho, he, 0x07030501u);   // (h + 128) >> 8: each lane's high byte
       }
+      out.store((size_t)y * W + xc, v);
     }
-    return ((acc[0] + 128u) >> 8) | (((acc[1] + 128u) >> 8) << 8) | (((acc[2] + 128u) >> 8) << 16) |
-           (((acc[3] + 128u) >> 8) << 24);
   }
-  if (op == kOpMed5 && y >= 1 && y <= H - 2 && x0 >= 4 && x0 + 8 <= W) {
-    const uint8_t *row = a + (size_t)y * W + x0;
-    const uint32_t wl = *(const uint32_t *)(row - 4), wc = *(const uint32_t *)row, wr = *(const uint32_t *)(row + 4);
-    const uint32_t wu = *(const uint32_t *)(row - W), wd = *(const uint32_t *)(row + W);
-    uint32_t p[6];   // columns x0-1 .. x0+4 of row y
-    p[0] = byte_of(wl, 3);
+}
+
+// 5-pixel median (the pixel, up, down, left, right) of rows [ya, yb) at word
+// column c.  Rows 0 and H-1 are copied.  A step loads the centre words of
+// rows y0-1 .. y0+4 and the side words of rows y0 .. y0+3.
+__device__ void med_rows(const uint8_t *a, const PixelDst &out, int W, int H, uint32_t c, uint32_t G,
+                         int ya, int yb) {
+  const uint32_t xc = 4 * c, xl = c ? xc - 4 : xc, xr = c + 1 < G ? xc + 4 : xc;
+  const bool at_left = c == 0, at_right = c + 1 == G;
+  for (int y0 = ya; y0 < yb; y0 += kPixRows) {
+    uint32_t wc[kPixRows + 2], wl[kPixRows], wr[kPixRows];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) p[j + 1] = byte_of(wc, j);
-    p[5] = byte_of(wr, 0);
-    uint32_t v = 0;
+    for (int i = 0; i < kPixRows + 2; ++i)
+      wc[i] = *(const uint32_t *)(a + (size_t)min(max(y0 - 1 + i, 0), H - 1) * W + xc);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      v |= median5(p[j + 1], byte_of(wu, j), byte_of(wd, j), p[j], p[j + 2]) << (8 * j);
-    return v;
+    for (int i = 0; i < kPixRows; ++i) {
+      const uint8_t *row = a + (size_t)min(y0 + i, H - 1) * W;
+      wl[i] = *(const uint32_t *)(row + xl);
+      wr[i] = *(const uint32_t *)(row + xr);
+    }
+#pragma unroll
+    for (int j = 0; j < kPixRows; ++j) {
+      const int y = y0 + j;
+      if (y >= yb) break;
+      const uint32_t wu = wc[j], wm = wc[j + 1], wd = wc[j + 2];
+      uint32_t v = wm;
+      if (y >= 1 && y <= H - 2) {
+        const uint32_t l = at_left ? rep_first(wm) : wl[j], r = at_right ? rep_last(wm) : wr[j];
+        const uint32_t wlft = __builtin_amdgcn_alignbyte(wm, l, 3u);   // columns x-1 .. x+2
+        const uint32_t wrgt = __builtin_amdgcn_alignbyte(r, wm, 1u);   // columns x+1 .. x+4
+        const uint32_t me = lanes_median5(lanes_even(wu), lanes_even(wd), lanes_even(wlft), lanes_even(wrgt),
+                                          lanes_even(wm));
+        const uint32_t mo = lanes_median5(lanes_odd(wu), lanes_odd(wd), lanes_odd(wlft), lanes_odd(wrgt),
+                                          lanes_odd(wm));
+        v = lanes_pack(me, mo);
+      }
+      out.store((size_t)y * W + xc, v);
+    }
   }
-  uint32_t v = 0;
+}
+
+// Thres: 255 where |a - b| > T, else 0, of rows [ya, yb) at word column c.
+// Per lane, d + (0x7fff - T) reaches bit 15 exactly when d > T (T clamped
+// to 255, d <= 255).
+__device__ void thres_rows(const uint8_t *a, const uint8_t *b, const PixelDst &out, int W, int H, uint32_t c,
+                           int ya, int yb, uint32_t T) {
+  const uint32_t bias = 0x7fffu - min(T, 255u), bias2 = bias | (bias << 16);
+  for (int y0 = ya; y0 < yb; y0 += kPixRows) {
+    uint32_t wa[kPixRows], wb[kPixRows];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) v |= pixel_op(op, a, b, k0 + j, W, H, T) << (8 * j);
-  return v;
+    for (int i = 0; i < kPixRows; ++i) {
+      const size_t k = (size_t)min(y0 + i, H - 1) * W + 4 * c;
+      wa[i] = *(const uint32_t *)(a + k);
+      wb[i] = *(const uint32_t *)(b + k);
+    }
+#pragma unroll
+    for (int j = 0; j < kPixRows; ++j) {
+      if (y0 + j >= yb) break;
+      uint32_t r[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const uint32_t la = p ? lanes_odd(wa[j]) : lanes_even(wa[j]);
+        const uint32_t lb = p ? lanes_odd(wb[j]) : lanes_even(wb[j]);
+        const uint32_t d = lanes_max(la, lb) - lanes_min(la, lb);
+        const uint32_t f = ((d + bias2) & 0x80008000u) >> 15;   // 0 or 1 per lane
+        r[p] = (f << 8) - f;                                   // 0 or 255 per lane
+      }
+      out.store((size_t)(y0 + j) * W + 4 * c, lanes_pack(r[0], r[1]));
+    }
+  }
 }
 
 // Items with a nonzero power (POLY outputs) store |v|^power * v; pixel
@@ -590,25 +675,39 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
     __syncthreads();
     if (threadIdx.x == 0) s_ci = items[it];
     __syncthreads();
+    if (s_ci.op != kOpCopy) {
+      // A pixel item covers a W x H byte frame (W a multiple of 4, frame
+      // bases word aligned), in chunks of kPixChunkRows rows taken
+      // grid-stride over blockIdx.y.  Threads split into P row groups of
+      // G = W / 4 word columns; each thread runs down its column over its
+      // run of the chunk's rows.
+      const int W = (int)s_ci.width, H = (int)(s_ci.count / s_ci.width);
+      const uint32_t G = (uint32_t)W / 4u;
+      const uint32_t P = max(1u, blockDim.x / G);
+      const uint32_t ty = threadIdx.x / G, tx = threadIdx.x - ty * G;
+      if (ty >= P) continue;
+      const uint8_t *a = (const uint8_t *)s_ci.src[0];
+      const uint8_t *b = (const uint8_t *)s_ci.src[1];
+      const uint32_t nd = s_ci.n_dst;
+      const PixelDst out{(uint8_t *)s_ci.dst, nd > 1 ? (uint8_t *)s_ci.src[2] : nullptr, &s_ci, nd};
+      const uint32_t cstep = P == 1 ? blockDim.x : G;
+      for (int y_lo = (int)(blockIdx.y * kPixChunkRows); y_lo < H; y_lo += (int)(gridDim.y * kPixChunkRows)) {
+        const int y_hi = min(H, y_lo + (int)kPixChunkRows);
+        const int rpt = (y_hi - y_lo + (int)P - 1) / (int)P;
+        const int ya = y_lo + (int)ty * rpt, yb = min(y_hi, ya + rpt);
+        for (uint32_t c = tx; c < G && ya < yb; c += cstep) {
+          if (s_ci.op == kOpGauss5) gauss_rows(a, out, W, H, c, G, ya, yb);
+          else if (s_ci.op == kOpMed5) med_rows(a, out, W, H, c, G, ya, yb);
+          else thres_rows(a, b, out, W, H, c, ya, yb, s_ci.param);
+        }
+      }
+      continue;
+    }
     const uint32_t halo_count = s_ci.halo_count, n_src = s_ci.n_src, power = s_ci.pad;
     const uint32_t total = halo_count + s_ci.count;
     const uint32_t lo = blockIdx.y * kCopyChunk;
     if (lo >= total) continue;
     const uint32_t hi = min(total, lo + kCopyChunk);
-    if (s_ci.op != kOpCopy) {
-      const uint8_t *a = (const uint8_t *)s_ci.src[0];
-      const uint8_t *b = (const uint8_t *)s_ci.src[1];
-      const int W = (int)s_ci.width, H = (int)(s_ci.count / s_ci.width);
-      const uint32_t op = s_ci.op, T = s_ci.param, nd = s_ci.n_dst;
-      // four consecutive pixels per thread (W and the frame bases are
-      // multiples of 4, so a group never leaves its row or splits a word)
-      for (uint32_t k = lo + 4 * threadIdx.x; k < hi; k += 4 * blockDim.x) {
-        const uint32_t v = pixel4(op, a, b, k, W, H, T);
-        *(uint32_t *)((uint8_t *)s_ci.dst + k) = v;
-        for (uint32_t q = 1; q < nd; ++q) *(uint32_t *)((uint8_t *)s_ci.src[q + 1] + k) = v;
-      }
-      continue;
-    }
     float2 *dst = s_ci.dst;
     for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
       float2 v;
@@ -698,10 +797,15 @@ void launch_control(const CtrlArgs &c, uint32_t n_comp, hipStream_t s) {
 }
 
 void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x,
-                 uint32_t max_total, hipStream_t s) {
-  const uint32_t gy = (max_total + kCopyChunk - 1) / kCopyChunk;
+                 uint32_t max_total, uint32_t pix_rows, hipStream_t s) {
+  // Element copies run up to 4096 workgroups that loop over the items.
+  // Pixel frames take a workgroup per item and row chunk (as many as 64K):
+  // their items are few and each stages its descriptor once.
+  const uint32_t gy = std::max((max_total + kCopyChunk - 1) / kCopyChunk,
+                               (pix_rows + kPixChunkRows - 1) / kPixChunkRows);
   if (!grid_x || !gy) return;
-  const uint32_t gx = std::min<uint32_t>(grid_x, std::max<uint32_t>(1, 4096 / gy));
+  const uint32_t budget = pix_rows ? 65536u : 4096u;
+  const uint32_t gx = std::min<uint32_t>(grid_x, std::max<uint32_t>(1, budget / gy));
   hipLaunchKernelGGL(k_copy, dim3(gx, gy), dim3(256), 0, s, items, n_items);
 }
 

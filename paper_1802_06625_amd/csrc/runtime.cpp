@@ -138,6 +138,7 @@ struct prune_graph {
            *d_single_off = nullptr;
   std::vector<char> level_fb, level_copy;
   std::vector<uint32_t> fb_item_off, fb_item_cap, copy_item_off, copy_item_cap, copy_max_total;
+  std::vector<uint32_t> copy_pix_rows;   // per level: most rows of a pixel actor's frame
   std::vector<uint32_t> post_actors;
   uint32_t *d_post_actors = nullptr;
   // scratch
@@ -612,6 +613,8 @@ uint32_t out_accesses(const prune_graph *g, const HActor &a) {
   return n;
 }
 
+bool is_pixel_kind(uint32_t k) { return k == PRUNE_GAUSS5 || k == PRUNE_THRES || k == PRUNE_MED5; }
+
 bool is_copy_kind(uint32_t k) {
   return k == PRUNE_SWITCH || k == PRUNE_POLY || k == PRUNE_SELECT || k == PRUNE_PASSTHROUGH || k == PRUNE_SOURCE ||
          k == PRUNE_GAUSS5 || k == PRUNE_THRES || k == PRUNE_MED5 ||
@@ -627,6 +630,7 @@ prune_status alloc_scratch(prune_graph *g) {
   g->fb_item_cap.assign(nl, 0);
   g->copy_item_cap.assign(nl, 0);
   g->copy_max_total.assign(nl, 0);
+  g->copy_pix_rows.assign(nl, 0);
   std::vector<uint32_t> desc_off(na, 0), halo_off(na, 0), level_of(na, 0);
   g->gather_cap.assign(nl, 0);
   uint32_t ndesc = 0, nhalo = 0;
@@ -645,8 +649,11 @@ prune_status alloc_scratch(prune_graph *g) {
       g->level_copy[A.level] = 1;
       uint32_t items = std::max<uint32_t>(1, out_accesses(g, A));
       g->copy_item_cap[A.level] += Bc * items;
-      g->copy_max_total[A.level] = std::max(g->copy_max_total[A.level],
-                                            std::max(max_out_atr(g, A), in_atr(g, A)));
+      if (is_pixel_kind(A.kind))
+        g->copy_pix_rows[A.level] = std::max(g->copy_pix_rows[A.level], A.pix.H);
+      else
+        g->copy_max_total[A.level] = std::max(g->copy_max_total[A.level],
+                                              std::max(max_out_atr(g, A), in_atr(g, A)));
     }
     if (A.hist_len) {
       halo_off[a] = nhalo;
@@ -780,21 +787,6 @@ void fb_launch_timed(prune_graph *g, uint32_t level, uint32_t grid, hipStream_t 
   if (g_timing) g_events.push_back({e0, e1});
 }
 
-// Launch the data kernels of one level (halo gathers first: they read input
-// blocks written by earlier levels).
-void launch_level(prune_graph *g, uint32_t l, hipStream_t s, uint32_t fb_grid_cap,
-                  uint32_t copy_items_cap, uint32_t B) {
-  const uint32_t nl = g->n_levels;
-  if (g->gather_cap[l] && B > 1) launch_gather(make_args(g, B), l, std::min<uint32_t>(g->gather_cap[l], 256), s);
-  if (g->level_copy[l])
-    launch_copy(g->d_copy + g->copy_item_off[l], g->d_ctr + nl + l,
-                std::min(g->copy_item_cap[l], copy_items_cap), g->copy_max_total[l], s);
-  if (g->level_fb[l]) {
-    uint32_t grid = std::min<uint32_t>(g->fb_grid, std::max<uint32_t>(1, fb_grid_cap));
-    fb_launch_timed(g, l, grid, s);
-  }
-}
-
 void timing_reset() {
   for (auto &e : g_events) {
     hipEventDestroy(e.first);
@@ -891,7 +883,8 @@ prune_status fire_one(prune_graph *g, uint32_t aid, hipStream_t s) {
                             (A.kind == PRUNE_SOURCE && src_ptr != nullptr);
     if (needs_copy)
       launch_copy(g->d_copy + g->copy_item_off[l], g->d_ctr + g->n_levels + l,
-                  std::max<uint32_t>(1, out_accesses(g, A)), max_count, s);
+                  std::max<uint32_t>(1, out_accesses(g, A)), is_pixel_kind(A.kind) ? 0 : max_count,
+                  is_pixel_kind(A.kind) ? A.pix.H : 0, s);
   }
   if (A.hist_len) launch_post(c, g->d_iota + aid, 1, s);
   // FIFOs with an unaligned delay: copy the overflow of this write back
@@ -1026,7 +1019,7 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
         launch_gather(make_args(g, B), l, std::min<uint32_t>(g->gather_cap[l], 256), st);
       if ((cmask & bit) && g->level_copy[l])
         launch_copy(g->d_copy + g->copy_item_off[l], g->d_ctr + g->n_levels + l,
-                    g->copy_item_cap[l], g->copy_max_total[l], st);
+                    g->copy_item_cap[l], g->copy_max_total[l], g->copy_pix_rows[l], st);
       if (g->level_fb[l]) fb_launch_timed(g, l, g->fb_grid, st);
     }
     launch_post(c, g->d_post_actors, (uint32_t)g->post_actors.size(), st);

@@ -87,8 +87,11 @@ struct BatchArgs {
 void launch_batch(const CtrlArgs &c, const BatchArgs &b, uint32_t n_comp, uint32_t n_actors,
                   hipStream_t s);
 void launch_control(const CtrlArgs &c, uint32_t n_comp, hipStream_t s);
+// Copy-kernel launch for one level: grid_x item slots, element chunks for
+// copies of up to max_total 8-byte words, row chunks for pixel frames of up
+// to pix_rows rows.
 void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x,
-                 uint32_t max_total, hipStream_t s);
+                 uint32_t max_total, uint32_t pix_rows, hipStream_t s);
 void launch_post(const CtrlArgs &c, const uint32_t *actors, uint32_t n, hipStream_t s);
 void launch_gather(const CtrlArgs &c, uint32_t level, uint32_t grid, hipStream_t s);
 void launch_clear(uint32_t *p, uint32_t n, hipStream_t s);

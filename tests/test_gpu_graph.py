@@ -353,3 +353,76 @@ def test_motion_detection_1080p():
     v = synth.make_video(3)
     dev = _run_motion_device(v, 4, L.BATCHED, trace=False)
     assert np.array_equal(dev["y"], mo.motion_stream(v))
+
+
+def _run_pixel_actor(kind, W, H, frames, other=None, threshold=20, mode=L.BATCHED, C=4):
+    """One pixel actor between sources and a sink (THRES takes two sources:
+    its first input and the frame it is compared with)."""
+    from paper_1802_06625_amd.graph import Graph
+    F = frames.shape[0]
+    npix = W * H
+    g = Graph(0)
+    act = g.actor(kind, L.PixelParams(W, H, threshold))
+    n_in = 2 if kind == L.THRES else 1
+    srcs = [g.actor(L.SOURCE) for _ in range(n_in)]
+    snk = g.actor(L.SINK)
+    P = lambda a, d: g.port(a, d, L.SRP, npix, token_bytes=1)
+    ins = [P(act, L.IN) for _ in range(n_in)]
+    po = P(act, L.OUT)
+    fifos = [g.connect(P(s, L.OUT), q, npix) for s, q in zip(srcs, ins)]
+    fifos.append(g.connect(po, P(snk, L.IN), npix))
+    g.finalize(C)
+    keep = []
+    for f in fifos:
+        t = torch.zeros(g.required_bytes(f), dtype=torch.uint8, device="cuda")
+        g.bind_storage(f, t)
+        keep.append(t)
+    out = torch.zeros(F * npix, dtype=torch.uint8, device="cuda")
+    g.sink_bind_output(snk, out)
+    data = [frames] + ([other] if n_in == 2 else [])
+    for s, d in zip(srcs, data):
+        t = torch.from_numpy(np.ascontiguousarray(d).reshape(-1)).cuda()
+        keep.append(t)
+        g.source_push(s, t, np.full(F, npix))
+    g.fire(mode)
+    g.sync()
+    return out.cpu().numpy().reshape(F, H, W)
+
+
+PIXEL_SIZES = [(4, 2), (8, 1), (4, 6), (12, 2), (8, 5), (40, 24), (520, 9), (1028, 6), (1920, 11)]
+
+
+@pytest.mark.parametrize("W,H", PIXEL_SIZES)
+def test_pixel_actors_each_against_oracle(W, H):
+    """Gauss, Med and Thres alone on full-range random bytes (every rounding
+    case of Gauss, medians of arbitrary values), at widths of one word,
+    edge-column and border-row cases, word-column counts below, between
+    and above one workgroup, and several row chunks."""
+    from oracle import motion as mo
+    announce(f"pixel actors {W}x{H}")
+    rng = np.random.default_rng(W * 1000 + H)
+    F = 3
+    a = rng.integers(0, 256, size=(F, H, W), dtype=np.uint8)
+    b = np.clip(a.astype(np.int64) + rng.integers(-40, 41, size=a.shape), 0, 255).astype(np.uint8)
+    got = _run_pixel_actor(L.GAUSS5, W, H, a)
+    for k in range(F):
+        assert np.array_equal(got[k], mo.gauss5(a[k])), ("gauss", k)
+    got = _run_pixel_actor(L.MED5, W, H, a)
+    for k in range(F):
+        assert np.array_equal(got[k], mo.med5(a[k])), ("med", k)
+    for T in (0, 20, 254, 255, 300):
+        got = _run_pixel_actor(L.THRES, W, H, a, b, threshold=T)
+        for k in range(F):
+            assert np.array_equal(got[k], mo.thres(a[k], b[k], T)), ("thres", T, k)
+
+
+@pytest.mark.parametrize("mode", [L.PER_FIRING, L.BATCHED_GRAPH])
+def test_pixel_actors_other_modes(mode):
+    from oracle import motion as mo
+    announce(f"pixel actors 40x24 mode={mode}")
+    rng = np.random.default_rng(7)
+    a = rng.integers(0, 256, size=(5, 24, 40), dtype=np.uint8)
+    got = _run_pixel_actor(L.GAUSS5, 40, 24, a, mode=mode, C=2)
+    assert all(np.array_equal(got[k], mo.gauss5(a[k])) for k in range(5))
+    got = _run_pixel_actor(L.MED5, 40, 24, a, mode=mode, C=3)
+    assert all(np.array_equal(got[k], mo.med5(a[k])) for k in range(5))
