@@ -532,7 +532,7 @@ struct PixelDst {
 // load of a step before using any of them, so that each wave keeps many
 // loads in flight.  Rows outside the frame are clamped (in bounds; such rows
 // only feed copied border rows).
-constexpr int kPixRows = 4;
+constexpr int kPixRows = 8;
 // Rows of a pixel frame per chunk of the grid's y dimension.
 constexpr uint32_t kPixChunkRows = 16;
 

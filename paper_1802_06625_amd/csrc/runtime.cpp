@@ -647,7 +647,8 @@ prune_status alloc_scratch(prune_graph *g) {
     }
     if (is_copy_kind(A.kind)) {
       g->level_copy[A.level] = 1;
-      uint32_t items = std::max<uint32_t>(1, out_accesses(g, A));
+      // a pixel firing is one item that stores to every FIFO of its output
+      uint32_t items = is_pixel_kind(A.kind) ? 1 : std::max<uint32_t>(1, out_accesses(g, A));
       g->copy_item_cap[A.level] += Bc * items;
       if (is_pixel_kind(A.kind))
         g->copy_pix_rows[A.level] = std::max(g->copy_pix_rows[A.level], A.pix.H);
