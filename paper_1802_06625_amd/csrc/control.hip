@@ -667,6 +667,9 @@ __device__ void thres_rows(const uint8_t *a, const uint8_t *b, const PixelDst &o
 // items (op != kOpCopy) run a Motion Detection actor over a byte frame.  The
 // item is staged in LDS so that its source list is indexed there rather
 // than in per-lane scratch.
+// Instantiated with the pixel path only for levels that hold pixel actors:
+// element copies keep the smaller register footprint (and occupancy).
+template <bool kPixels>
 __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items,
                                               const uint32_t *__restrict__ n_items) {
   __shared__ CopyItem s_ci;
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
     __syncthreads();
     if (threadIdx.x == 0) s_ci = items[it];
     __syncthreads();
-    if (s_ci.op != kOpCopy) {
+    if (kPixels && s_ci.op != kOpCopy) {
       // A pixel item covers a W x H byte frame (W a multiple of 4, frame
       // bases word aligned), in chunks of kPixChunkRows rows taken
       // grid-stride over blockIdx.y.  Threads split into P row groups of
@@ -806,7 +809,10 @@ void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x
   if (!grid_x || !gy) return;
   const uint32_t budget = pix_rows ? 65536u : 4096u;
   const uint32_t gx = std::min<uint32_t>(grid_x, std::max<uint32_t>(1, budget / gy));
-  hipLaunchKernelGGL(k_copy, dim3(gx, gy), dim3(256), 0, s, items, n_items);
+  if (pix_rows)
+    hipLaunchKernelGGL(k_copy<true>, dim3(gx, gy), dim3(256), 0, s, items, n_items);
+  else
+    hipLaunchKernelGGL(k_copy<false>, dim3(gx, gy), dim3(256), 0, s, items, n_items);
 }
 
 void launch_post(const CtrlArgs &c, const uint32_t *actors, uint32_t n, hipStream_t s) {

@@ -39,10 +39,12 @@ template <int J>
 __device__ __forceinline__ int pidx(int i) { return i + i / J; }
 
 // Coefficient table layout: tap-major, coef[l * kMaxKH + b], so the
-// coefficients of a chunk are at constant offsets from one base.
+// coefficients of a chunk are at constant offsets from one base.  Chunk c
+// holds taps cJ .. cJ+J-1; the last one holds only L - (nchunks-1) J real
+// taps (the rest are zero padding) and stops there.
 template <int KH, int J>
 __device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
-                                            const float2 *__restrict__ coef, int Lpad,
+                                            const float2 *__restrict__ coef, int Lpad, int L,
                                             int t, float *accr, float *acci) {
   const int nchunks = Lpad / J;
   const float4 *wl = win + t * (J + 1);   // this lane's part of the window index
@@ -61,6 +63,7 @@ __device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
     }
 #pragma unroll
     for (int i = 0; i < J; ++i) {
+      if (c * J + i >= L) break;   // uniform: zero-padded taps of the last chunk
       float2 cf[KH];
 #pragma unroll
       for (int b = 0; b < KH; ++b) cf[b] = cb[i * kMaxKH + b];
@@ -84,18 +87,18 @@ __device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
 
 template <int J>
 __device__ __forceinline__ void horner_dispatch(int KH, const float4 *win, const float2 *coef,
-                                                int Lpad, int t, float *accr, float *acci) {
+                                                int Lpad, int L, int t, float *accr, float *acci) {
   switch (KH) {
-    case 1: horner_pass<1, J>(win, coef, Lpad, t, accr, acci); break;
-    case 2: horner_pass<2, J>(win, coef, Lpad, t, accr, acci); break;
-    case 3: horner_pass<3, J>(win, coef, Lpad, t, accr, acci); break;
-    case 4: horner_pass<4, J>(win, coef, Lpad, t, accr, acci); break;
-    case 5: horner_pass<5, J>(win, coef, Lpad, t, accr, acci); break;
-    case 6: horner_pass<6, J>(win, coef, Lpad, t, accr, acci); break;
-    case 7: horner_pass<7, J>(win, coef, Lpad, t, accr, acci); break;
-    case 8: horner_pass<8, J>(win, coef, Lpad, t, accr, acci); break;
-    case 9: horner_pass<9, J>(win, coef, Lpad, t, accr, acci); break;
-    default: horner_pass<10, J>(win, coef, Lpad, t, accr, acci); break;
+    case 1: horner_pass<1, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 2: horner_pass<2, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 3: horner_pass<3, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 4: horner_pass<4, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 5: horner_pass<5, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 6: horner_pass<6, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 7: horner_pass<7, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 8: horner_pass<8, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 9: horner_pass<9, J>(win, coef, Lpad, L, t, accr, acci); break;
+    default: horner_pass<10, J>(win, coef, Lpad, L, t, accr, acci); break;
   }
 }
 
@@ -229,7 +232,7 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
           it_next = s_next[par ^ 1u];
           prefetch(it_next);   // in flight during the compute below
         }
-        horner_dispatch<J>(KH, win, coef, Lpad, t, accr, acci);
+        horner_dispatch<J>(KH, win, coef, Lpad, L, t, accr, acci);
       }
 #pragma unroll
       for (int j = 0; j < J; ++j) {
