@@ -99,6 +99,10 @@ struct HActor {
   std::deque<prune_side_info> side_q;
   void *q_dev = nullptr;
   uint64_t q_cap = 0, q_tail = 0, q_head = 0;
+  // Queue entries below q_synced are known to be read by the device; those in
+  // [q_synced, q_head) may still be read by bookkeeping in flight (fire calls
+  // return before the device runs them).
+  uint64_t q_synced = 0;
   float2 *history = nullptr;
   uint32_t hist_len = 0;
   float2 *taps = nullptr;
@@ -923,6 +927,12 @@ prune_status check_graph(prune_graph *g, bool need_final, bool need_device = tru
 
 prune_status ensure_ring(prune_graph *g, HActor &A, size_t entry, uint64_t need) {
   (void)g;
+  // a write that would reach ring positions of entries the device may not
+  // have read yet waits for the device first
+  if (A.q_dev && A.q_tail + need > A.q_synced + A.q_cap) {
+    HIPCHECK(hipDeviceSynchronize());
+    A.q_synced = A.q_head;
+  }
   const uint64_t live = A.q_tail - A.q_head;
   if (A.q_dev && live + need <= A.q_cap) return PRUNE_OK;
   uint64_t cap = std::max<uint64_t>(1024, A.q_cap);
@@ -948,6 +958,7 @@ prune_status ensure_ring(prune_graph *g, HActor &A, size_t entry, uint64_t need)
   if (A.q_dev) HIPCHECK(hipFree(A.q_dev));
   A.q_dev = nq;
   A.q_cap = cap;
+  A.q_synced = A.q_head;   // the device was synchronized above
   return PRUNE_OK;
 }
 

@@ -91,6 +91,19 @@ def test_modes_mixed_across_rounds():
     compare_stats(dev["g"], logs_ref)
 
 
+def test_queue_ring_wraps_while_batches_are_in_flight():
+    """26 rounds of push-then-fire without synchronizing: the input queues
+    wrap their 1024-entry rings while earlier batches' bookkeeping may still
+    be queued on the device; every frame still comes out as the oracle's."""
+    announce("queue ring wrap with batches in flight (C1, 1300 frames x 64)")
+    wl = synth.make("C1", n_frames=1300, frame_len=64)
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=64)
+    dev = run_plain_device(wl, 64, L.BATCHED, batches=26, src_rounds=True)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+    compare_stats(dev["g"], logs_ref)
+
+
 def test_inplace_source_frames():
     announce("in-place source frames (C2-scaled)")
     wl = synth.scaled("C2")
