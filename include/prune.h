@@ -414,17 +414,22 @@ prune_status prune_graph_stream_host(prune_graph_t g, prune_id src, prune_id cfg
  * f (equal to atr for an SRP, 1..atr for a PRUNE_PORT_PARAM port).
  * dev_samples: device pointer to the frames back to back (copied into the
  * FIFO when the source fires; must stay valid until then), or NULL when the
- * caller has already written frame f at prune_fifo_write_window(f). */
+ * caller has already written frame f at prune_fifo_write_window(f).
+ * Queued entries live in a device ring; a push that would overwrite entries
+ * the device may not have read yet (fire calls return before the device
+ * runs them) synchronizes the device first. */
 prune_status prune_source_push(prune_graph_t g, prune_id src, const void *dev_samples,
                                const uint32_t *host_counts, uint32_t n_frames);
 
-/* Queue n_frames firings of configuration actor `cfg` with host side-info. */
+/* Queue n_frames firings of configuration actor `cfg` with host side-info
+ * (same ring rule as prune_source_push). */
 prune_status prune_config_push(prune_graph_t g, prune_id cfg, const prune_side_info *host_side,
                                uint32_t n_frames, prune_stream_t stream);
 
 /* Optional: every firing of sink `snk` copies its tokens to dev_out at the
  * running token offset (cap_tokens tokens available).  Without a bound
- * output the tokens stay in the FIFO storage. */
+ * output the tokens stay in the FIFO storage.  Synchronizes the device
+ * first: batches in flight read the binding. */
 prune_status prune_sink_bind_output(prune_graph_t g, prune_id snk, void *dev_out,
                                     uint64_t cap_tokens);
 

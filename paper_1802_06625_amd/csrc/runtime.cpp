@@ -1465,6 +1465,8 @@ prune_status prune_config_push(prune_graph_t g, prune_id cfg, const prune_side_i
 prune_status prune_sink_bind_output(prune_graph_t g, prune_id snk, void *dev_out, uint64_t cap) {
   TRY(check_graph(g, true));
   if (snk >= g->actors.size() || g->actors[snk].kind != PRUNE_SINK) return fail(PRUNE_E_ARG, "not a sink");
+  // batches in flight read the binding when their bookkeeping runs
+  HIPCHECK(hipDeviceSynchronize());
   g->actors[snk].sink_out = dev_out;
   g->actors[snk].sink_cap = dev_out ? cap : 0;
   return sync_actor_dev(g, snk);
