@@ -264,7 +264,8 @@ extern int forced_variant();
 int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
   const int forced = forced_variant();
   if (forced) return forced;
-  const uint32_t Lc = (L + 7) / 8 * 8;
+  // the exact tap count: kernels with different tap chunks pad L differently
+  const uint32_t Lc = L;
   const uint32_t nc = n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512);
   const auto key = std::make_tuple(Lc, K, nc);
   {
