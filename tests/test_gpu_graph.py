@@ -152,6 +152,25 @@ def test_routed_multistream(mode):
     compare_stats(dev["g"], logs_ref)
 
 
+def test_routed_pipeline_on_off_identical():
+    """Routed graph (switch and select copies, halo gathers, a level with
+    both copy items and a filter bank) over several batches (C=3): the same
+    bits and logs with the bookkeeping on the side stream as on the caller's
+    stream."""
+    announce("routed C5-scaled, batch pipeline on/off, C=3")
+    from paper_1802_06625_amd import ops
+    wl = synth.scaled("C5")
+    try:
+        ops.set_batch_pipeline(False)
+        a = run_routed_device(wl, 3, L.BATCHED)
+    finally:
+        ops.set_batch_pipeline(True)
+    b = run_routed_device(wl, 3, L.BATCHED)
+    assert np.array_equal(a["y"], b["y"])
+    assert a["fifos"] == b["fifos"]
+    assert a["ctrl"] == b["ctrl"]
+
+
 def test_rate_beyond_atr_is_reported():
     """A control token whose rate exceeds atr surfaces at sync as E_TOKEN
     (the firing moves no tokens, so no access leaves the FIFO blocks)."""
