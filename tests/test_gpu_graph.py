@@ -458,3 +458,59 @@ def test_pixel_actors_other_modes(mode):
     assert all(np.array_equal(got[k], mo.gauss5(a[k])) for k in range(5))
     got = _run_pixel_actor(L.MED5, 40, 24, a, mode=mode, C=3)
     assert all(np.array_equal(got[k], mo.med5(a[k])) for k in range(5))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_plain_random_configurations(seed):
+    """Seeded sweep over the plain graph's knobs against the oracle: workload
+    (fixed or uneven frames, three banks), frame count, FIFO depth C, branch
+    sets (prefix or arbitrary), execution mode per round, number of rounds
+    and whether source frames are pushed per round."""
+    rng = np.random.default_rng(1000 + seed)
+    name = ["C1", "C3"][int(rng.integers(0, 2))]
+    F = int(rng.integers(1, 41))
+    C = int(rng.integers(2, 10))
+    rounds = int(rng.integers(1, 5))
+    modes = [[L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH][int(rng.integers(0, 3))] for _ in range(rounds)]
+    src_rounds = bool(rng.integers(0, 2)) or L.PER_FIRING in modes[:-1]
+    masks = bool(rng.integers(0, 2))
+    announce(f"random plain config seed={seed}: {name} F={F} C={C} modes={modes} "
+             f"src_rounds={src_rounds} masks={masks}")
+    if name == "C1":
+        wl = synth.make("C1", seed=seed, n_frames=F, frame_len=int(rng.integers(1, 9)) * 64)
+        kw = {}
+    else:
+        wl = synth.make("C3", seed=seed, n_frames=F, n_max=int(rng.integers(64, 1500)))
+        kw = dict(param=True, atr=int(wl.spec.n_max))
+        N = int(wl.side[0, :, 1].sum())
+        wl.x = wl.x[:, :N].copy()
+    cfg = "prefix"
+    if masks:
+        wl.side[0, :, 0] = rng.integers(0, 1 << wl.Kmax, size=F)
+        cfg = "mask"
+    y_ref, logs_ref, _, ids = og.run_plain(wl, C=C, cfg_mode=cfg, **kw)
+    dev = run_plain_device(wl, C, modes, batches=rounds, src_rounds=src_rounds,
+                           cfg_mode=L.CONFIG_MASK if masks else L.CONFIG_PREFIX, **kw)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["fb"]])
+    compare_stats(dev["g"], logs_ref)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_routed_random_configurations(seed):
+    """Seeded sweep over the routed multi-stream graph: stream count, frame
+    count and length, FIFO depth C and execution mode, against the oracle."""
+    rng = np.random.default_rng(2000 + seed)
+    S = int(rng.integers(1, 5))
+    F = int(rng.integers(1, 13))
+    n = [256, 512, 1024][int(rng.integers(0, 3))]
+    C = int(rng.integers(2, 7))
+    mode = [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH][int(rng.integers(0, 3))]
+    announce(f"random routed config seed={seed}: S={S} F={F} n={n} C={C} mode={mode}")
+    wl = synth.make("C5", seed=seed, n_streams=S, n_frames=F, frame_len=n)
+    y_ref, logs_ref, _, ids = og.run_routed(wl, C=C)
+    dev = run_routed_device(wl, C, mode)
+    for s in range(S):
+        assert rel_l2(dev["y"][s], y_ref[s]) <= TOL, s
+    compare_logs(dev, logs_ref, [i["sw"] for i in ids] + [i["sel"] for i in ids])
+    compare_stats(dev["g"], logs_ref)
