@@ -514,3 +514,27 @@ def test_routed_random_configurations(seed):
         assert rel_l2(dev["y"][s], y_ref[s]) <= TOL, s
     compare_logs(dev, logs_ref, [i["sw"] for i in ids] + [i["sel"] for i in ids])
     compare_stats(dev["g"], logs_ref)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_motion_random_configurations(seed):
+    """Seeded sweep over the Motion Detection graph: frame width (a multiple
+    of 4) and height, frame count, FIFO depth C (the delay FIFO lowers the
+    batch cap) and execution mode; random bytes, so every actor sees
+    arbitrary values.  Motion maps and FIFO logs bit-exact."""
+    rng = np.random.default_rng(3000 + seed)
+    while True:
+        W = 4 * int(rng.integers(1, 17))
+        H = int(rng.integers(1, 21))
+        if (W * H) % 8 == 0:
+            break
+    F = int(rng.integers(1, 11))
+    C = int(rng.integers(2, 7))
+    mode = [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH][int(rng.integers(0, 3))]
+    announce(f"random motion config seed={seed}: {W}x{H} F={F} C={C} mode={mode}")
+    v = rng.integers(0, 256, size=(F, H, W), dtype=np.uint8)
+    y_ref, logs_ref, _, _ = og.run_motion(v, C=C)
+    dev = _run_motion_device(v, C, mode)
+    assert np.array_equal(dev["y"], y_ref)
+    compare_logs(dev, logs_ref, [])
+    compare_stats(dev["g"], logs_ref)
