@@ -184,3 +184,59 @@ def test_backward_frames_with_gaps(form):
         for (t0, n, m, r) in ref:
             read[max(0, t0 - (L - 1)):t0 + n] = True
         assert np.all(gx[s_][~read] == 0)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_direct_ops_random_configurations(seed):
+    """Seeded sweep over the whole-stream operations: streams, banks, Kmax,
+    a tap count per bank (1..64), frames of 1..3000 samples with gaps,
+    arbitrary branch masks, passthrough frames and a forward variant; forward
+    and both adjoint forms against the oracle."""
+    from oracle.filterbank import fb_stream
+    rng = np.random.default_rng(4000 + seed)
+    S = int(rng.integers(1, 4))
+    n_banks = int(rng.integers(1, 4))
+    Kmax = int(rng.integers(1, 11))
+    bank_L = tuple(int(v) for v in rng.integers(1, 65, size=n_banks))
+    Lmax = max(bank_L)
+    D = n_banks * Kmax
+    variant = int(rng.integers(0, 9))
+    announce(f"direct ops seed={seed}: S={S} banks={bank_L} Kmax={Kmax} variant={variant}")
+    taps = ((rng.standard_normal((S, n_banks, Kmax, Lmax)) + 1j * rng.standard_normal((S, n_banks, Kmax, Lmax)))
+            / (4 * Lmax)).astype(np.complex64)
+    for b, L in enumerate(bank_L):
+        taps[:, b, :, L:] = 0
+    rows, N = [], 1
+    for s in range(S):
+        t = int(rng.integers(0, 100))
+        for _ in range(int(rng.integers(1, 7))):
+            n = int(rng.integers(1, 3001))
+            rows.append((s, t, n, int(rng.integers(0, 1 << D)), int(rng.random() < 0.15)))
+            t += n + (0 if rng.random() < 0.5 else int(rng.integers(1, 100)))
+        N = max(N, t + int(rng.integers(0, 50)))
+    x = ((rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))) * 0.3).astype(np.complex64)
+    gy = (rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))).astype(np.complex64)
+    mfl = max(n for (_, _, n, _, _) in rows)
+    fr = ops.frame_table(rows)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda()
+    ops.set_variant(variant)
+    try:
+        y = ops.fb_forward(xd, td, fr, Kmax, bank_L, mfl)
+        torch.cuda.synchronize()
+    finally:
+        ops.set_variant(0)
+    y = y.cpu().numpy()
+    for form in BWD_FORMS:
+        gx, gt = _backward(xd, td, fr, torch.from_numpy(gy).cuda(), Kmax, bank_L, mfl, form)
+        for s in range(S):
+            ref = [(t0, n, m, r) for (ss, t0, n, m, r) in rows if ss == s]
+            if form == BWD_FORMS[0]:
+                # outputs outside every frame are not written: compare the frames' outputs
+                ry = fb_stream(x[s], ref, taps[s], bank_L, Kmax)
+                cov = np.zeros(N, bool)
+                for (t0, n, m, r) in ref:
+                    cov[t0:t0 + n] = True
+                assert rel_l2(y[s][cov], ry[cov]) <= TOL, ("forward", s)
+            rx, rt = fb_stream_adjoint(x[s], ref, taps[s], bank_L, Kmax, gy[s])
+            assert rel_l2(gx[s], rx) <= TOL, (form, s, rel_l2(gx[s], rx))
+            assert rel_l2(gt[s], rt) <= TOL, (form, s, rel_l2(gt[s], rt))
