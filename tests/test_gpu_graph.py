@@ -538,3 +538,22 @@ def test_motion_random_configurations(seed):
     assert np.array_equal(dev["y"], y_ref)
     compare_logs(dev, logs_ref, [])
     compare_stats(dev["g"], logs_ref)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_unfused_random_configurations(seed):
+    """Seeded sweep over the unfused DPD graph: workload recipe (Kmax 4 or 10,
+    L 8, 10 or 32), frame count and length, FIFO depth C and mode."""
+    rng = np.random.default_rng(5000 + seed)
+    name = ["C1", "C2", "P"][int(rng.integers(0, 3))]
+    F = int(rng.integers(1, 13))
+    n = int(rng.integers(1, 9)) * 128
+    C = int(rng.integers(2, 9))
+    mode = [L.PER_FIRING, L.BATCHED, L.BATCHED_GRAPH][int(rng.integers(0, 3))]
+    announce(f"random unfused config seed={seed}: {name} F={F} n={n} C={C} mode={mode}")
+    wl = synth.make(name, seed=seed, n_frames=F, frame_len=n)
+    y_ref, logs_ref, ids = _run_unfused_oracle(wl, C)
+    dev = _run_unfused_device(wl, C, mode)
+    assert rel_l2(dev["y"], y_ref) <= TOL
+    compare_logs(dev, logs_ref, [ids["poly"], ids["add"]])
+    compare_stats(dev["g"], logs_ref)
