@@ -708,35 +708,36 @@ __global__ __launch_bounds__(256) void k_copy(const CopyItem *__restrict__ items
     }
     const uint32_t halo_count = s_ci.halo_count, n_src = s_ci.n_src, power = s_ci.pad;
     const uint32_t total = halo_count + s_ci.count;
-    const uint32_t lo = blockIdx.y * kCopyChunk;
-    if (lo >= total) continue;
-    const uint32_t hi = min(total, lo + kCopyChunk);
     float2 *dst = s_ci.dst;
-    for (uint32_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-      float2 v;
-      if (k < halo_count) {
-        v = s_ci.halo[k];
-      } else {
-        const uint32_t s = k - halo_count;
-        if (n_src == 1) {
-          v = s_ci.src[0][s];   // a copy moves the bits (byte frames too), no arithmetic
+    // chunks of kCopyChunk words, grid-stride over blockIdx.y
+    for (uint64_t lo = (uint64_t)blockIdx.y * kCopyChunk; lo < total; lo += (uint64_t)gridDim.y * kCopyChunk) {
+      const uint64_t hi = min((uint64_t)total, lo + kCopyChunk);
+      for (uint64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        float2 v;
+        if (k < halo_count) {
+          v = s_ci.halo[k];
         } else {
-          v = make_float2(0.f, 0.f);
-          for (uint32_t q = 0; q < n_src; ++q) {
-            const float2 u = s_ci.src[q][s];
-            v.x += u.x;
-            v.y += u.y;
+          const uint64_t s = k - halo_count;
+          if (n_src == 1) {
+            v = s_ci.src[0][s];   // a copy moves the bits (byte frames too), no arithmetic
+          } else {
+            v = make_float2(0.f, 0.f);
+            for (uint32_t q = 0; q < n_src; ++q) {
+              const float2 u = s_ci.src[q][s];
+              v.x += u.x;
+              v.y += u.y;
+            }
           }
         }
+        if (power) {
+          const float r = sqrtf(v.x * v.x + v.y * v.y);
+          float m = r;
+          for (uint32_t e = 1; e < power; ++e) m *= r;
+          v.x *= m;
+          v.y *= m;
+        }
+        dst[k] = v;
       }
-      if (power) {
-        const float r = sqrtf(v.x * v.x + v.y * v.y);
-        float m = r;
-        for (uint32_t e = 1; e < power; ++e) m *= r;
-        v.x *= m;
-        v.y *= m;
-      }
-      dst[k] = v;
     }
   }
 }
@@ -804,8 +805,10 @@ void launch_copy(const CopyItem *items, const uint32_t *n_items, uint32_t grid_x
   // Element copies run up to 4096 workgroups that loop over the items.
   // Pixel frames take a workgroup per item and row chunk (as many as 64K):
   // their items are few and each stages its descriptor once.
-  const uint32_t gy = std::max((max_total + kCopyChunk - 1) / kCopyChunk,
-                               (pix_rows + kPixChunkRows - 1) / kPixChunkRows);
+  // both paths take their chunks grid-stride over y, so the grid's y extent
+  // can stay within its limit
+  const uint32_t gy = std::min<uint32_t>(65535u, std::max((max_total + kCopyChunk - 1) / kCopyChunk,
+                                                          (pix_rows + kPixChunkRows - 1) / kPixChunkRows));
   if (!grid_x || !gy) return;
   const uint32_t budget = pix_rows ? 65536u : 4096u;
   const uint32_t gx = std::min<uint32_t>(grid_x, std::max<uint32_t>(1, budget / gy));
