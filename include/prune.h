@@ -261,7 +261,8 @@ prune_status prune_control_table_set(prune_graph_t g, prune_id ctrl_port, prune_
 /* Validate the graph (Sec. III local rules, rule 4 of Sec. IV, the actor
  * kinds' rate relations) and size every FIFO by Eq. 2 with constant C.
  * Allocates library-owned device state (counters, control FIFOs, histories,
- * taps, work lists).  Errors as listed with the status codes. */
+ * taps, work lists).  Errors as listed with the status codes; E_UNSUPPORTED
+ * for more than 65535 actors. */
 prune_status prune_graph_finalize(prune_graph_t g, uint32_t C);
 
 /* ---- compile-time analysis (Sec. IV design rules, Sec. V) --------------- */

@@ -1299,6 +1299,8 @@ prune_status prune_control_table_set(prune_graph_t g, prune_id ctl, prune_id drp
 prune_status prune_graph_finalize(prune_graph_t g, uint32_t C) {
   TRY(check_graph(g, false));
   if (C == 0) return fail(PRUNE_E_ARG, "C must be positive");
+  // the batch kernels put actors (and components) on a grid's y dimension
+  if (g->actors.size() > 65535) return fail(PRUNE_E_UNSUPPORTED, "at most 65535 actors per graph");
   if (g->checks & PRUNE_CHECK_RULES) {
     run_design_analysis(g);
     if (!g->report.violations.empty()) {
