@@ -165,6 +165,17 @@ def test_unsupported_shapes():
     assert e.value.code == L.E_UNSUPPORTED
 
 
+def test_actor_count_limit():
+    g = Graph(-1)
+    lib, h = L.lib(), g.h
+    out = C.c_uint32()
+    for _ in range(65536):
+        assert lib.prune_actor_create(h, L.PASSTHROUGH, None, 0, C.byref(out)) == L.OK
+    with pytest.raises(L.PruneError) as e:
+        g.finalize(2)
+    assert e.value.code == L.E_UNSUPPORTED
+
+
 def test_variant_selection_arguments():
     """Forward and backward kernel selection: valid indices are accepted,
     others rejected with E_ARG, and the names are stable."""
