@@ -346,6 +346,30 @@ def test_host_stream(batch, C):
     assert e.value.code == L.E_ARG
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_host_stream_random_configurations(seed):
+    """Seeded sweep over host streaming: batch size, ring depth (a multiple
+    of the batch holding at least two), frame length, frame count (also not
+    a multiple of the batch) and how the stream is split over calls."""
+    rng = np.random.default_rng(6000 + seed)
+    batch = int(rng.integers(1, 17))
+    C = batch * int(rng.integers(2, 5))
+    F = int(rng.integers(1, 61))
+    n = int(rng.integers(1, 9)) * 64
+    cuts = sorted(set(int(v) for v in rng.integers(0, F + 1, size=int(rng.integers(0, 3)))) | {0, F})
+    announce(f"random host stream seed={seed}: batch={batch} C={C} F={F} n={n} cuts={cuts}")
+    from paper_1802_06625_amd.graph import PlainGraph
+    wl = synth.make("C1", seed=seed, n_frames=F, frame_len=n)
+    y_ref, _, _, _ = og.run_plain(wl, C=3)
+    pg = PlainGraph(wl.Kmax, wl.bank_L, n, C)
+    pg.g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    hin = torch.from_numpy(wl.x[0]).pin_memory()
+    hout = torch.zeros(hin.shape, dtype=hin.dtype).pin_memory()
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        pg.g.stream_host(pg.src, pg.cfg, pg.snk, hin[a * n:b * n], wl.side[0, a:b], hout[a * n:b * n], batch)
+    assert rel_l2(hout.numpy(), y_ref) <= TOL
+
+
 # ---------------------------------------------------------------- Motion Detection
 def _run_motion_device(frames, C, mode, trace=True):
     from paper_1802_06625_amd.graph import MotionGraph, trace_logs
