@@ -117,8 +117,8 @@ def cpu_baseline(wl, budget_s, gpu_first_frames):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the single-GPU path is the "
-                                   "measured one (see the sharding notes); --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs one graph on one GPU and this benchmark "
+                                   "measures that single-GPU path; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import synth

@@ -59,7 +59,8 @@ def test_parity_dpg_structures(seed):
 
 
 def test_random_structures_cover_every_code():
-    """The seeds above exercise every violation code and both verdicts."""
+    """The seeds above exercise every violation code, clean graphs and
+    deadlocking ones."""
     seen, clean, deadlocks = set(), 0, 0
     for seed in range(150):
         for S in (gg.random_structure(seed), gg.dpg_structure(seed)):
