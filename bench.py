@@ -316,8 +316,12 @@ def bench_direct(name, steps, warmup):
                        device="cuda")
     fwd = lambda: ops.fb_forward(x, taps, fr, wl.Kmax, wl.bank_L, mfl, y=y)
     bwd = lambda: ops.fb_backward(x, taps, fr, gy, wl.Kmax, wl.bank_L, mfl, gx=gx, gt=gt, work=work)
+    # the adjoint as a tap fit uses it: grad_taps only (grad_x not computed)
+    bwd_taps = lambda: ops.fb_backward(x, taps, fr, gy, wl.Kmax, wl.bank_L, mfl, gt=gt, work=work,
+                                       want_gx=False)
     t_f = _time_events(fwd, steps, warmup)
     t_b = _time_events(bwd, steps, warmup)
+    t_bt = _time_events(bwd_taps, steps, warmup)
     bwd_by_form = {}
     for form in (1, 2):
         ops.set_bwd_variant(form)
@@ -347,6 +351,8 @@ def bench_direct(name, steps, warmup):
            "fwd_msamples": round(samples / (t_f * 1e-3) / 1e6, 1),
            "fwd_bwd_msamples": round(samples / ((t_f + t_b) * 1e-3) / 1e6, 1),
            "fwd_ms": round(t_f, 4), "bwd_ms": round(t_b, 4),
+           "fwd_bwd_taps_only_msamples": round(samples / ((t_f + t_bt) * 1e-3) / 1e6, 1),
+           "bwd_taps_only_ms": round(t_bt, 4),
            "fwd_tflops_alg": round(f_fwd / (t_f * 1e-3) / 1e12, 2),
            "bwd_tflops_alg": round(f_bwd / (t_b * 1e-3) / 1e12, 2),
            "fwd_bwd_frac_of_fp32_vector_peak": round((f_fwd + f_bwd) / ((t_f + t_b) * 1e-3) / 1e12

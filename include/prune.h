@@ -524,7 +524,10 @@ prune_status prune_fb_workspace_bytes(const prune_fb_desc *desc, size_t *bytes);
  * gx [S][N] and gtaps [S][n_banks][Kmax][Lmax] (entries beyond a bank's L
  * are written as zero) from the cotangent gy [S][N].  The |x|^p basis is
  * recomputed, not stored.  workspace: device buffer of at least
- * prune_fb_workspace_bytes bytes (tile partials and halo gradients). */
+ * prune_fb_workspace_bytes bytes (tile partials and halo gradients).
+ * Either gx or gtaps may be NULL to skip that gradient (E_ARG if both are);
+ * without gx only the matrix-core grad_h kernel and its reductions run,
+ * whichever adjoint form is selected. */
 prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const void *taps,
                                const void *frames, const void *gy, void *gx, void *gtaps,
                                void *workspace, size_t workspace_bytes, prune_stream_t stream);

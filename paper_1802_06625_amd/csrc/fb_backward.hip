@@ -574,6 +574,7 @@ prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const v
                                void *workspace, size_t workspace_bytes, prune_stream_t stream) {
   prune_status st = check_bwd_desc(desc);
   if (st != PRUNE_OK) return st;
+  if (!x || !taps || !frames || !gy || (!gx && !gtaps) || !workspace) return PRUNE_E_ARG;
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
   const int v = choose_bwd_variant(Lmax, desc->Kmax, desc->max_frame_len);
@@ -610,7 +611,8 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
                                         const void *frames, const void *gy, void *gx, void *gtaps,
                                         void *workspace, size_t workspace_bytes, int variant,
                                         prune_stream_t stream) {
-  if (!x || !taps || !frames || !gy || !gx || !gtaps || !workspace) return PRUNE_E_ARG;
+  // either gradient may be skipped (a null output), not both
+  if (!x || !taps || !frames || !gy || (!gx && !gtaps) || !workspace) return PRUNE_E_ARG;
   const BwdLayout L = bwd_layout(*desc);
   if (workspace_bytes < L.total) return PRUNE_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
@@ -625,9 +627,9 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   unsigned long long *cov = (unsigned long long *)(w + L.cov);
   const prune_fb_desc d = *desc;
   if (d.n_frames == 0) {
-    if (hipMemsetAsync(gx, 0, (size_t)d.n_streams * d.stream_len * sizeof(float2), s) != hipSuccess)
+    if (gx && hipMemsetAsync(gx, 0, (size_t)d.n_streams * d.stream_len * sizeof(float2), s) != hipSuccess)
       return PRUNE_E_HIP;
-    if (hipMemsetAsync(gtaps, 0, (size_t)d.n_streams * L.E * sizeof(float2), s) != hipSuccess)
+    if (gtaps && hipMemsetAsync(gtaps, 0, (size_t)d.n_streams * L.E * sizeof(float2), s) != hipSuccess)
       return PRUNE_E_HIP;
     return PRUNE_OK;
   }
@@ -635,27 +637,33 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
                      (const prune_fb_frame *)frames, (const float2 *)gy, (float2 *)gx, bf, items, cnt,
                      sb, se, cov);
   // grad_x starts as zero outside the frames' coverage
-  hipLaunchKernelGGL(k_bwd_gapfill, dim3(d.n_streams, 64), dim3(256), 0, s, d, cov, (float2 *)gx);
+  if (gx) hipLaunchKernelGGL(k_bwd_gapfill, dim3(d.n_streams, 64), dim3(256), 0, s, d, cov, (float2 *)gx);
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
-  if (variant == 2) {
+  // Without grad_x only the matrix-core grad_h kernel runs (the vector
+  // kernel computes both gradients in one pass).
+  const bool mfma = variant == 2 || !gx;
+  if (mfma) {
     // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids at
     // the kernels' occupancy (3 and 2 workgroups per CU)
-    launch_bwd_gu_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg,
-                       std::min<uint32_t>(L.max_items + d.n_frames, (uint32_t)ncu * 3), s);
-    launch_bwd_gh_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 2), partial, L.max_items,
-                       (uint32_t)ncu * 2, s);
+    if (gx)
+      launch_bwd_gu_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg,
+                         std::min<uint32_t>(L.max_items + d.n_frames, (uint32_t)ncu * 3), s);
+    if (gtaps)
+      launch_bwd_gh_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 2), partial, L.max_items,
+                         (uint32_t)ncu * 2, s);
   } else {
     hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
   }
-  if (L.H) {
-    if (variant != 2)   // the matrix-core grad_x kernel computes the halo rows itself
+  if (gx && L.H) {
+    if (!mfma)   // the matrix-core grad_x kernel computes the halo rows itself
       hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
     hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
                        bf, hg, (float2 *)gx);
   }
+  if (!gtaps) return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
   const uint32_t eblocks = (L.E + 63) / 64;
   hipLaunchKernelGGL(k_bwd_reduce1, dim3(d.n_streams, eblocks, kRedG), dim3(256), 0, s, d, partial, sb,
                      se, part2);

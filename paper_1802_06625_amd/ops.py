@@ -93,7 +93,10 @@ def workspace_bytes(S, N, Kmax, bank_L, n_frames, max_frame_len):
     return ws.value
 
 
-def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len, gx=None, gt=None, work=None):
+def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len, gx=None, gt=None, work=None,
+                want_gx=True, want_gt=True):
+    """Adjoint of fb_forward: (grad_x, grad_taps); a gradient not wanted is
+    not computed and returned as None."""
     S, N = x.shape
     x = x.contiguous()
     taps = taps.contiguous()
@@ -103,13 +106,19 @@ def fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, max_frame_len, gx=None, g
     call("prune_fb_workspace_bytes", C.byref(d), C.byref(ws))
     if work is None or work.numel() < ws.value:
         work = torch.empty(max(1, ws.value), dtype=torch.uint8, device=x.device)
-    if gx is None:
+    if gx is None and want_gx:
         gx = torch.empty_like(x)
-    if gt is None:
+    if gt is None and want_gt:
         gt = torch.empty_like(taps)
+    if not want_gx:
+        gx = None
+    if not want_gt:
+        gt = None
     call("prune_fb_backward", C.byref(d), C.c_void_p(x.data_ptr()), C.c_void_p(taps.data_ptr()),
-         C.c_void_p(frames_dev.data_ptr()), C.c_void_p(gy.data_ptr()), C.c_void_p(gx.data_ptr()),
-         C.c_void_p(gt.data_ptr()), C.c_void_p(work.data_ptr()), ws.value, _stream())
+         C.c_void_p(frames_dev.data_ptr()), C.c_void_p(gy.data_ptr()),
+         C.c_void_p(gx.data_ptr() if gx is not None else None),
+         C.c_void_p(gt.data_ptr() if gt is not None else None), C.c_void_p(work.data_ptr()), ws.value,
+         _stream())
     return gx, gt
 
 
@@ -128,9 +137,11 @@ class FilterBankFn(torch.autograd.Function):
     def backward(ctx, gy):
         x, taps, frames_dev = ctx.saved_tensors
         Kmax, bank_L, mfl = ctx.cfg
-        gx, gt = fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, mfl)
-        return (gx if ctx.needs_input_grad[0] else None,
-                gt if ctx.needs_input_grad[1] else None, None, None, None, None)
+        want_gx, want_gt = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (want_gx or want_gt):
+            return None, None, None, None, None, None
+        gx, gt = fb_backward(x, taps, frames_dev, gy, Kmax, bank_L, mfl, want_gx=want_gx, want_gt=want_gt)
+        return gx, gt, None, None, None, None
 
 
 def filter_bank(x, taps, frames_dev, Kmax, bank_L, max_frame_len):

@@ -196,3 +196,12 @@ def test_variant_selection_arguments():
     v = C.c_int()
     assert lib.prune_autotune_bwd(0, 7, 1024, C.byref(v)) == L.E_ARG
     assert lib.prune_autotune_bwd(65, 7, 1024, C.byref(v)) == L.E_ARG
+
+
+def test_backward_needs_one_gradient_output():
+    """prune_fb_backward checks its pointers before any device work: both
+    gradient outputs null is an argument error (no GPU needed)."""
+    from paper_1802_06625_amd import ops
+    d = ops.make_desc(1, 1024, 4, (8,), 1, 1024)
+    p = C.c_void_p(16)   # never dereferenced: the call returns before any device work
+    assert L.lib().prune_fb_backward(C.byref(d), p, p, p, p, None, None, p, 1 << 20, None) == L.E_ARG

@@ -240,3 +240,31 @@ def test_direct_ops_random_configurations(seed):
             rx, rt = fb_stream_adjoint(x[s], ref, taps[s], bank_L, Kmax, gy[s])
             assert rel_l2(gx[s], rx) <= TOL, (form, s, rel_l2(gx[s], rx))
             assert rel_l2(gt[s], rt) <= TOL, (form, s, rel_l2(gt[s], rt))
+
+
+@pytest.mark.parametrize("form", BWD_FORMS)
+def test_backward_optional_gradients(form):
+    """A gradient that is not wanted is not computed: grad_x alone equals the
+    grad_x of the full call bit for bit; grad_taps alone comes from the
+    matrix-core grad_h kernel (equal bit for bit to the full call's in that
+    form) and matches the oracle in either form."""
+    announce(f"backward optional gradients form {form}")
+    wl = synth.scaled("C4", cotangent=True)
+    rows = _rows(wl)
+    fr = ops.frame_table(rows)
+    mfl = int(wl.side[:, :, 1].max())
+    x, t, gy = (torch.from_numpy(a).cuda() for a in (wl.x, wl.taps, wl.gy))
+    ops.set_bwd_variant(form)
+    try:
+        gx_full, gt_full = ops.fb_backward(x, t, fr, gy, wl.Kmax, wl.bank_L, mfl)
+        gx_only, none1 = ops.fb_backward(x, t, fr, gy, wl.Kmax, wl.bank_L, mfl, want_gt=False)
+        none2, gt_only = ops.fb_backward(x, t, fr, gy, wl.Kmax, wl.bank_L, mfl, want_gx=False)
+        torch.cuda.synchronize()
+    finally:
+        ops.set_bwd_variant(0)
+    assert none1 is None and none2 is None
+    assert torch.equal(gx_only, gx_full)
+    if form == 2:
+        assert torch.equal(gt_only, gt_full)
+    _, rt = fb_stream_adjoint(wl.x[0], stream_frames(wl, 0), wl.taps[0], wl.bank_L, wl.Kmax, wl.gy[0])
+    assert rel_l2(gt_only.cpu().numpy()[0], rt) <= TOL
