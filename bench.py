@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-per-frame", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--only-c2", action="store_true", help="skip the other workloads")
-    p.add_argument("--only", default="", help="run one secondary workload only: c3, c4, c5, c5bwd")
+    p.add_argument("--only", default="", help="run one secondary workload only: c3, c4, c4fit, c5, c5bwd, c2u, paper, host, motion")
     p.add_argument("--copy-calib", action="store_true",
                    help="only copy a 1 GiB buffer twice (HBM counter calibration)")
     p.add_argument("--profile-only", action="store_true",
@@ -130,6 +130,7 @@ def main():
     if args.only:
         fn = {"c3": lambda: bench_c3(args.steps, args.warmup),
               "c4": lambda: bench_direct("C4", args.steps, args.warmup),
+              "c4fit": lambda: bench_fit(),
               "c5": lambda: bench_c5(args.steps, args.warmup),
               "c5bwd": lambda: bench_direct("C5", args.steps, args.warmup),
               "c2u": lambda: bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), None),
@@ -267,6 +268,7 @@ def main():
         out["paper_dpd"] = bench_paper_dpd(min(args.steps, 10), min(args.warmup, 5))
         print("bench: fwd+bwd (differentiation workload)", file=sys.stderr, flush=True)
         out["c4_fwd_bwd"] = bench_direct("C4", args.steps, args.warmup)
+        out["c4_fit"] = bench_fit()
         print("bench: batched uneven frames", file=sys.stderr, flush=True)
         out["c3_batched"] = bench_c3(args.steps, args.warmup)
         print("bench: routed multi-stream graph", file=sys.stderr, flush=True)
@@ -293,6 +295,52 @@ def _time_events(fn, steps, warmup):
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def bench_fit(steps=200, lr=1e-2):
+    """The differentiation workload as a tap fit: full-batch Adam on the taps
+    of the amplifier-fit workload (256 x 8192, K=8, L=16) through the
+    autograd Function (forward + grad_taps kernels), loss computed in torch.
+    The step time includes torch's loss and Adam kernels; the target's noise
+    (per-component sigma 0.01) puts the loss floor near 2e-4."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import ops
+    wl = synth.make("C4")
+    rows = ops.frames_from_side(wl.side, wl.Kmax, False)
+    fr = ops.frame_table(rows)
+    mfl = int(wl.side[:, :, 1].max())
+    x = torch.from_numpy(wl.x).cuda()
+    target = torch.from_numpy(wl.target).cuda()
+    taps = torch.nn.Parameter(torch.from_numpy(wl.taps).cuda().clone())
+    opt = torch.optim.Adam([taps], lr=lr)
+
+    def step():
+        y = ops.filter_bank(x, taps, fr, wl.Kmax, wl.bank_L, mfl)
+        e = y - target
+        loss = torch.mean(e.real ** 2 + e.imag ** 2)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        return loss
+
+    losses = [float(step().detach())]     # first step untimed (allocations)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st = torch.cuda.current_stream()
+    vals = []
+    e0.record(st)
+    for _ in range(steps - 1):
+        vals.append(step().detach())
+    e1.record(st)
+    torch.cuda.synchronize()
+    losses += [float(v) for v in vals]
+    ms = e0.elapsed_time(e1) / (steps - 1)
+    samples = int(wl.x.size)
+    return {"workload": wl.spec.description + f", {steps} Adam steps lr {lr}",
+            "ms_per_step": round(ms, 4), "msamples_per_s": round(samples / (ms * 1e-3) / 1e6, 1),
+            "loss_by_step": {str(k): round(losses[k], 6) for k in (0, 10, 50, 100, steps - 1)},
+            "loss_noise_floor": 2e-4}
 
 
 def bench_direct(name, steps, warmup):
