@@ -205,3 +205,19 @@ def test_backward_needs_one_gradient_output():
     d = ops.make_desc(1, 1024, 4, (8,), 1, 1024)
     p = C.c_void_p(16)   # never dereferenced: the call returns before any device work
     assert L.lib().prune_fb_backward(C.byref(d), p, p, p, p, None, None, p, 1 << 20, None) == L.E_ARG
+
+
+def test_pixel_actor_parameters():
+    """Motion Detection actors: frame width a multiple of 4 (the kernels move
+    words of four pixels), W*H a multiple of 8 (copies move 8-byte words),
+    positive sizes, and a parameter block of the right size."""
+    g = Graph(-1)
+    for kind in (L.GAUSS5, L.THRES, L.MED5):
+        assert g.actor(kind, L.PixelParams(40, 24, 20)) >= 0
+        for (W, H), code in [((42, 24), L.E_UNSUPPORTED), ((4, 1), L.E_ARG), ((0, 8), L.E_ARG),
+                             ((8, 0), L.E_ARG)]:
+            with pytest.raises(L.PruneError) as e:
+                g.actor(kind, L.PixelParams(W, H, 20))
+            assert e.value.code == code, (kind, W, H)
+        out = C.c_uint32()
+        assert L.lib().prune_actor_create(g.h, kind, None, 0, C.byref(out)) == L.E_ARG
