@@ -581,3 +581,50 @@ def test_unfused_random_configurations(seed):
     assert rel_l2(dev["y"], y_ref) <= TOL
     compare_logs(dev, logs_ref, [ids["poly"], ids["add"]])
     compare_stats(dev["g"], logs_ref)
+
+
+@pytest.mark.parametrize("name", ["C2", "C3"])
+def test_full_size_graph_sampled_frames(name):
+    """The measured configuration: the plain graph at full size (C2: 4096 x
+    16384, L=32; C3: 2048 uneven frames up to 65536, three banks), C equal
+    to the batch, frames written in place, two consecutive pipelined batched
+    firings of the same batch as consecutive bench steps fire it.  Sampled
+    frames of the second batch against the oracle, frame by frame, with the
+    stream's true history (the first batch's last frame for frame 0)."""
+    from oracle.filterbank import fb_frame
+    from oracle.graphs import stream_frames
+    from paper_1802_06625_amd.graph import PlainGraph
+    announce(f"full-size {name} graph, two pipelined batches, sampled frames")
+    wl = synth.make(name)
+    side = wl.side[0]
+    F = side.shape[0]
+    n = side[:, 1].astype(np.int64)
+    param = bool(np.any(n != n[0]))
+    atr = int(wl.spec.n_max) if param else int(n[0])
+    pg = PlainGraph(wl.Kmax, wl.bank_L, atr, F, param)
+    g = pg.g
+    g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    off = np.concatenate([[0], np.cumsum(n)])
+    blocks_in = pg.fifo_in.view(-1, atr)
+    x = torch.from_numpy(wl.x[0])
+    for f in range(F):
+        blocks_in[f, :n[f]].copy_(x[off[f]:off[f + 1]])
+    for _ in range(2):
+        g.source_push(pg.src, None, n)
+        g.config_push(pg.cfg, side)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.fire(L.BATCHED, F)
+    g.sync()
+    out = pg.fifo_out.view(-1, atr)
+    frames = stream_frames(wl, 0)
+    H = max(wl.bank_L) - 1
+    stream = np.concatenate([wl.x[0], wl.x[0]])
+    total = int(off[-1])
+    rng = np.random.default_rng(1)
+    for f in sorted(set(rng.choice(F, 6, replace=False).tolist()) | {0, F - 1}):
+        t0, nf, m, _ = frames[f]
+        t0 += total
+        ref = fb_frame(stream[t0 - H:t0 + nf], H, wl.taps[0], wl.bank_L, wl.Kmax, m)
+        got = out[f, :nf].cpu().numpy()
+        assert rel_l2(got, ref) <= TOL, (name, f, rel_l2(got, ref))
