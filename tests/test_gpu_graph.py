@@ -628,3 +628,80 @@ def test_full_size_graph_sampled_frames(name):
         ref = fb_frame(stream[t0 - H:t0 + nf], H, wl.taps[0], wl.bank_L, wl.Kmax, m)
         got = out[f, :nf].cpu().numpy()
         assert rel_l2(got, ref) <= TOL, (name, f, rel_l2(got, ref))
+
+
+def test_full_size_routed_graph_sampled_frames():
+    """The routed multi-stream graph at full C5 size (64 streams x 16 x
+    32768, K=7, L=64, about 30 % passthrough), C equal to the batch, two
+    consecutive pipelined batched firings as the bench fires them.  Sampled
+    frames of the second batch against the oracle frame by frame: filter-bank
+    frames from the stream's history (the switch sees every frame), and
+    passthrough frames equal to their input."""
+    from oracle.filterbank import fb_frame
+    from oracle.graphs import stream_frames
+    from paper_1802_06625_amd.graph import RoutedGraph
+    announce("full-size C5 routed graph, two pipelined batches, sampled frames")
+    wl = synth.make("C5")
+    S, F, n = wl.n_streams, wl.n_frames, int(wl.side[0, 0, 1])
+    rg = RoutedGraph(S, wl.Kmax, wl.bank_L, n, F)
+    g = rg.g
+    for s, ids in enumerate(rg.streams):
+        g.set_taps(ids["fb"], torch.from_numpy(wl.taps[s]).cuda())
+        rg.storage[s]["in"].view(F, n).copy_(torch.from_numpy(wl.x[s]).view(F, n))
+        for _ in range(2):
+            g.source_push(ids["src"], None, wl.side[s, :, 1])
+            g.config_push(ids["cfg"], wl.side[s])
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.fire(L.BATCHED, F)
+    g.sync()
+    H = max(wl.bank_L) - 1
+    rng = np.random.default_rng(2)
+    for s in sorted(rng.choice(S, 8, replace=False).tolist()):
+        out = rg.storage[s]["out"].view(F, n).cpu().numpy()
+        stream = np.concatenate([wl.x[s], wl.x[s]])
+        frames = stream_frames(wl, s)
+        for f in sorted(set(rng.choice(F, 3, replace=False).tolist()) | {0}):
+            t0, nf, m, r = frames[f]
+            t0 += F * n
+            if r:
+                np.testing.assert_array_equal(out[f], stream[t0:t0 + nf])
+                continue
+            ref = fb_frame(stream[t0 - H:t0 + nf], H, wl.taps[s], wl.bank_L, wl.Kmax, m)
+            assert rel_l2(out[f], ref) <= TOL, (s, f, rel_l2(out[f], ref))
+
+
+def test_full_size_motion_batches():
+    """Motion Detection at the measured size: 1920x1080 frames in batches of
+    64 (C = 65 for the one-frame delay FIFO), source frames in place, two
+    consecutive pipelined batched firings; sampled output frames of both
+    batches (the first, the batch boundary, the last) bit-exact against the
+    oracle's Gauss -> Thres -> Med on each firing's frame and its
+    predecessor."""
+    from oracle import motion as mo
+    from paper_1802_06625_amd.graph import MotionGraph
+    announce("full-size motion, two batches of 64 1080p frames, sampled frames")
+    W, H, B = 1920, 1080, 64
+    v = synth.make_video(8)
+    frames = np.stack([v[f % len(v)] for f in range(B)])
+    mg = MotionGraph(W, H, B + 1)
+    g = mg.g
+    npix = W * H
+    mg.fifo_in.view(-1, npix)[:B].copy_(torch.from_numpy(frames.reshape(B, npix)))
+    out = torch.zeros(2 * B * npix, dtype=torch.uint8, device="cuda")
+    g.sink_bind_output(mg.snk, out)
+    for _ in range(2):
+        g.source_push(mg.src, None, np.full(B, npix))
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.fire(L.BATCHED, B)
+    g.sync()
+    y = out.view(2 * B, H, W)
+    # firing j reads source block j mod C: blocks 0..B-1 hold the frames,
+    # block B was never written (zeros)
+    zero = np.zeros((H, W), np.uint8)
+    seq = [frames[j % (B + 1)] if j % (B + 1) < B else zero for j in range(2 * B)]
+    for k in [0, 1, 37, B - 1, B, B + 1, B + 50, 2 * B - 1]:
+        prev = mo.gauss5(seq[k - 1]) if k else np.zeros((H, W), np.uint8)
+        ref = mo.med5(mo.thres(mo.gauss5(seq[k]), prev))
+        assert np.array_equal(y[k].cpu().numpy(), ref), k
