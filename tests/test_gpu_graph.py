@@ -583,10 +583,11 @@ def test_unfused_random_configurations(seed):
     compare_stats(dev["g"], logs_ref)
 
 
-@pytest.mark.parametrize("name", ["C2", "C3"])
+@pytest.mark.parametrize("name", ["C2", "C3", "P"])
 def test_full_size_graph_sampled_frames(name):
     """The measured configuration: the plain graph at full size (C2: 4096 x
-    16384, L=32; C3: 2048 uneven frames up to 65536, three banks), C equal
+    16384, L=32; C3: 2048 uneven frames up to 65536, three banks; P: the
+    paper's DPD shape, 1024 x 65536, L=10), C equal
     to the batch, frames written in place, two consecutive pipelined batched
     firings of the same batch as consecutive bench steps fire it.  Sampled
     frames of the second batch against the oracle, frame by frame, with the
