@@ -294,7 +294,6 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
   } else if (kind == PRUNE_FILTERBANK) {
     const uint32_t H = fb->Lmax - 1;
     FbFrameDesc *D = c.fb_desc + c.desc_off[a];
-    uint32_t carry = 0;
     for (uint32_t base = 0; base < B; base += nt) {
       const uint32_t i = base + tid;
       uint32_t tiles = 0;
@@ -331,7 +330,6 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
         WorkItem w; w.frame = c.desc_off[a] + i; w.tile = k;
         c.fb_items[off + k] = w;
       }
-      carry += tot;
       __syncthreads();
     }
     // branch counters

@@ -186,8 +186,8 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
     sc = &g_scratch[dev];
     if (sc->cap_frames < desc->n_frames || sc->cap_items < items) {
       if (hipDeviceSynchronize() != hipSuccess) return PRUNE_E_HIP;
-      if (sc->desc) hipFree(sc->desc);
-      if (sc->items) hipFree(sc->items);
+      if (sc->desc) (void)hipFree(sc->desc);
+      if (sc->items) (void)hipFree(sc->items);
       if (!sc->ctr && hipMalloc((void **)&sc->ctr, 4 * sizeof(uint32_t)) != hipSuccess) return PRUNE_E_HIP;
       sc->cap_frames = std::max<size_t>(desc->n_frames, 2 * sc->cap_frames);
       sc->cap_items = std::max<size_t>(items, 2 * sc->cap_items);
@@ -203,12 +203,16 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
   const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 3, items);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timing_on() && !g_tuning;
-  if (timed) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+  if (timed) {   // events that cannot be created leave the launch untimed
+    if (hipEventCreate(&e0) != hipSuccess) e0 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) e1 = nullptr;
+    if (!e0 || !e1) {
+      timing_push(e0, e1);   // releases the one that exists
+      e0 = e1 = nullptr;
+    }
   }
   fb_forward_launch(variant, sc->desc, sc->items, sc->ctr, (unsigned int *)(sc->ctr + 1), grid, s, e0, e1);
-  if (timed) timing_push(e0, e1);
+  if (e0) timing_push(e0, e1);
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }
 }  // namespace prune

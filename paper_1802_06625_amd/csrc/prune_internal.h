@@ -62,7 +62,7 @@ __host__ __device__ inline bool fifo_can_write(uint32_t r, uint32_t Q, uint32_t 
   return (inflight + 1) * (int64_t)r <= (int64_t)r * C - (int64_t)Q;
 }
 
-__host__ __device__ inline bool fifo_can_read(uint32_t r, uint32_t Q, uint32_t C,
+__host__ __device__ inline bool fifo_can_read(uint32_t r, uint32_t Q, uint32_t /*C*/,
                                               int64_t inflight) {
   if (Q % r == 0) return (int64_t)(Q / r) + inflight > 0;
   return (int64_t)Q + inflight * (int64_t)r >= (int64_t)r;

@@ -39,7 +39,15 @@ namespace prune {
 int forced_variant() { return g_variant_forced; }
 // Kernel timing of the direct forward (prune_fb_forward) on this thread.
 bool timing_on() { return g_timing; }
-void timing_push(hipEvent_t e0, hipEvent_t e1) { g_events.push_back({e0, e1}); }
+// A launch is timed only when both of its events exist.
+void timing_push(hipEvent_t e0, hipEvent_t e1) {
+  if (e0 && e1) {
+    g_events.push_back({e0, e1});
+    return;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+}
 }  // namespace prune
 
 namespace {
@@ -194,19 +202,20 @@ struct prune_graph {
   ~prune_graph();
 };
 
+// Teardown reports nothing: errors here have no caller to go to.
 prune_graph::~prune_graph() {
-  if (side_stream) hipStreamSynchronize(side_stream);
+  if (side_stream) (void)hipStreamSynchronize(side_stream);
   for (hipEvent_t e : {ev_emit[0], ev_emit[1], ev_done[0], ev_done[1], ev_sync})
-    if (e) hipEventDestroy(e);
-  if (side_stream) hipStreamDestroy(side_stream);
-  for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
-  for (auto &kv : graph_defs) hipGraphDestroy(kv.second);
-  if (capture_stream) hipStreamDestroy(capture_stream);
-  for (void *p : owned) hipFree(p);
+    if (e) (void)hipEventDestroy(e);
+  if (side_stream) (void)hipStreamDestroy(side_stream);
+  for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : graph_defs) (void)hipGraphDestroy(kv.second);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  for (void *p : owned) (void)hipFree(p);
   for (auto &a : actors)
-    if (a.q_dev) hipFree(a.q_dev);
-  if (d_trace) hipFree(d_trace);
-  if (d_trace_count) hipFree(d_trace_count);
+    if (a.q_dev) (void)hipFree(a.q_dev);
+  if (d_trace) (void)hipFree(d_trace);
+  if (d_trace_count) (void)hipFree(d_trace_count);
 }
 
 namespace {
@@ -225,12 +234,6 @@ prune_status upload(prune_graph *g, T **p, const std::vector<T> &v) {
   TRY(dalloc(g, p, v.size()));
   if (!v.empty()) HIPCHECK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return PRUNE_OK;
-}
-
-bool is_dynamic(const prune_graph *g, const HActor &a) {
-  for (uint32_t p : a.ports)
-    if (g->ports[p].kind == PRUNE_CPORT) return true;
-  return false;
 }
 
 int64_t cport_fifo(const prune_graph *g, const HActor &a) {
@@ -783,19 +786,23 @@ CtrlArgs make_args(prune_graph *g, uint32_t B) {
 void fb_launch_timed(prune_graph *g, uint32_t level, uint32_t grid, hipStream_t s) {
   const uint32_t nl = g->n_levels;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_timing) {
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+  if (g_timing) {   // events that cannot be created leave the launch untimed
+    if (hipEventCreate(&e0) != hipSuccess) e0 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) e1 = nullptr;
+    if (!e0 || !e1) {
+      timing_push(e0, e1);   // releases the one that exists
+      e0 = e1 = nullptr;
+    }
   }
   fb_forward_launch(g->variant, g->d_desc, g->d_items + g->fb_item_off[level], g->d_ctr + level,
                     (unsigned int *)(g->d_ctr + 2 * nl + level), grid, s, e0, e1);
-  if (g_timing) g_events.push_back({e0, e1});
+  if (e0) timing_push(e0, e1);
 }
 
 void timing_reset() {
   for (auto &e : g_events) {
-    hipEventDestroy(e.first);
-    hipEventDestroy(e.second);
+    if (e.first) (void)hipEventDestroy(e.first);
+    if (e.second) (void)hipEventDestroy(e.second);
   }
   g_events.clear();
   g_fb_ms = 0.f;
@@ -1712,11 +1719,12 @@ prune_status prune_actor_firings(prune_graph_t g, prune_id actor, uint64_t *firi
 prune_status prune_trace_enable(prune_graph_t g, size_t max_records) {
   TRY(check_graph(g, true));
   HIPCHECK(hipDeviceSynchronize());
-  if (g->d_trace) { hipFree(g->d_trace); g->d_trace = nullptr; }
-  if (g->d_trace_count) { hipFree(g->d_trace_count); g->d_trace_count = nullptr; }
+  if (g->d_trace) { (void)hipFree(g->d_trace); g->d_trace = nullptr; }
+  if (g->d_trace_count) { (void)hipFree(g->d_trace_count); g->d_trace_count = nullptr; }
   g->trace_cap = 0;
-  for (auto &kv : g->graphs) hipGraphExecDestroy(kv.second);
-  for (auto &kv : g->graph_defs) hipGraphDestroy(kv.second);
+  // captured graphs hold the old trace pointers
+  for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : g->graph_defs) (void)hipGraphDestroy(kv.second);
   g->graphs.clear();
   g->graph_defs.clear();
   if (!max_records) return PRUNE_OK;
