@@ -264,11 +264,11 @@ namespace prune {
 extern int forced_variant();
 
 // Time each forward variant on a synthetic batch of the shape class and keep
-// the fastest.  Key: (L rounded up to a multiple of 8, K, frame length class).
+// the fastest.  Key: (L, K, frame length class); L is exact because the
+// kernels pad the tap count to different chunk sizes.
 int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
   const int forced = forced_variant();
   if (forced) return forced;
-  // the exact tap count: kernels with different tap chunks pad L differently
   const uint32_t Lc = L;
   const uint32_t nc = n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512);
   const auto key = std::make_tuple(Lc, K, nc);
