@@ -646,8 +646,9 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   // kernel computes both gradients in one pass).
   const bool mfma = variant == 2 || !gx;
   if (mfma) {
-    // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids at
-    // the kernels' occupancy (3 and 2 workgroups per CU)
+    // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids of
+    // 3 and 2 workgroups per CU, the fastest measured (at their register use
+    // the kernels keep 2 and 1 workgroups resident per CU)
     if (gx)
       launch_bwd_gu_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg,
                          std::min<uint32_t>(L.max_items + d.n_frames, (uint32_t)ncu * 3), s);
