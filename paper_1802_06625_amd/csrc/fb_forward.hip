@@ -14,10 +14,12 @@
 //
 // Data layout: frames are complex64 (float2) blocks in HBM.  A work item is
 // one tile of T = J*WG consecutive outputs of one frame.  The tile's input
-// window [n0 - (Lpad-1), n0 + T) is staged in LDS as float4 {re, im, r, 0}
-// with one pad float4 per J (lane t reads at stride J+1 float4, which puts the
-// 16 lanes of a 128-bit read in distinct banks, and makes every window and
-// coefficient read of a chunk a constant offset from one base).  Window positions before the frame come from
+// window [n0 - (Lpad-1), n0 + T) is staged in LDS as three fp32 planes (re,
+// im, r) with one pad element per J: lane t reads at stride J+1 words (9 or
+// 5, odd, so the lanes of a read fall in distinct banks), and every window
+// and coefficient read of a chunk is a constant offset from one base.  At
+// 12 bytes per window sample the J = 8, 256-thread kernel needs 33.6 KB of
+// LDS, so four workgroups fit on a CU, as many as its registers allow.  Window positions before the frame come from
 // the frame's halo (the stream's past samples), positions after the frame
 // are zero.  Each lane computes J consecutive outputs from a register window
 // of 2J-1 samples per chunk of J taps; the tap coefficients of the chunk are
@@ -31,10 +33,10 @@ namespace prune {
 
 constexpr int kMaxKH = 10;
 
-// Window layout: one pad float4 per J, so position t*J + k (k >= 0) is at
-// t*(J+1) + k + k/J: a per-lane part plus a part uniform across lanes.  Lanes
-// read 16-byte elements J+1 apart (80 or 144 bytes), which puts the 16 lanes
-// of a 128-bit read in distinct banks.
+// Window layout: one pad element per J in each plane, so position t*J + k
+// (k >= 0) is at t*(J+1) + k + k/J: a per-lane part plus a part uniform
+// across lanes.  Lanes read words J+1 apart, an odd stride, so they hit
+// distinct banks.
 template <int J>
 __device__ __forceinline__ int pidx(int i) { return i + i / J; }
 
@@ -43,23 +45,24 @@ __device__ __forceinline__ int pidx(int i) { return i + i / J; }
 // holds taps cJ .. cJ+J-1; the last one holds only L - (nchunks-1) J real
 // taps (the rest are zero padding) and stops there.
 template <int KH, int J>
-__device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
+__device__ __forceinline__ void horner_pass(const float *__restrict__ wre,
+                                            const float *__restrict__ wim,
+                                            const float *__restrict__ wrr,
                                             const float2 *__restrict__ coef, int Lpad, int L,
                                             int t, float *accr, float *acci) {
   const int nchunks = Lpad / J;
-  const float4 *wl = win + t * (J + 1);   // this lane's part of the window index
   for (int c = 0; c < nchunks; ++c) {
     // window positions t*J + k0 + w, k0 = Lpad - (c+1) J (a multiple of J)
     const int k0 = Lpad - c * J - J;
-    const float4 *wb = wl + k0 + k0 / J;
+    const int wb = t * (J + 1) + k0 + k0 / J;   // this lane's part plus the chunk's
     const float2 *cb = coef + c * J * kMaxKH;
     float xr[2 * J - 1], xi[2 * J - 1], rr[2 * J - 1];
 #pragma unroll
     for (int w = 0; w < 2 * J - 1; ++w) {
-      const float4 v = wb[w + w / J];
-      xr[w] = v.x;
-      xi[w] = v.y;
-      rr[w] = v.z;
+      const int q = wb + w + w / J;
+      xr[w] = wre[q];
+      xi[w] = wim[q];
+      rr[w] = wrr[q];
     }
 #pragma unroll
     for (int i = 0; i < J; ++i) {
@@ -86,19 +89,20 @@ __device__ __forceinline__ void horner_pass(const float4 *__restrict__ win,
 }
 
 template <int J>
-__device__ __forceinline__ void horner_dispatch(int KH, const float4 *win, const float2 *coef,
-                                                int Lpad, int L, int t, float *accr, float *acci) {
+__device__ __forceinline__ void horner_dispatch(int KH, const float *wre, const float *wim,
+                                                const float *wrr, const float2 *coef, int Lpad,
+                                                int L, int t, float *accr, float *acci) {
   switch (KH) {
-    case 1: horner_pass<1, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 2: horner_pass<2, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 3: horner_pass<3, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 4: horner_pass<4, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 5: horner_pass<5, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 6: horner_pass<6, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 7: horner_pass<7, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 8: horner_pass<8, J>(win, coef, Lpad, L, t, accr, acci); break;
-    case 9: horner_pass<9, J>(win, coef, Lpad, L, t, accr, acci); break;
-    default: horner_pass<10, J>(win, coef, Lpad, L, t, accr, acci); break;
+    case 1: horner_pass<1, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 2: horner_pass<2, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 3: horner_pass<3, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 4: horner_pass<4, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 5: horner_pass<5, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 6: horner_pass<6, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 7: horner_pass<7, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 8: horner_pass<8, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 9: horner_pass<9, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    default: horner_pass<10, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
   }
 }
 
@@ -115,7 +119,8 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
   constexpr int T = J * WG;
   constexpr int WMAX = T + PRUNE_MAX_L - 1;
   constexpr int NIT = (WMAX + WG - 1) / WG;   // window elements per thread
-  __shared__ float4 win[WMAX + WMAX / J + 1];
+  constexpr int WP = WMAX + WMAX / J + 1;   // window length with the pads
+  __shared__ float wre[WP], wim[WP], wrr[WP];
   __shared__ float2 coef[kMaxKH * PRUNE_MAX_L];
   __shared__ uint32_t s_next[2];
   const int t = threadIdx.x;
@@ -211,7 +216,12 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
 #pragma unroll
           for (int i = 0; i < NIT; ++i) {
             const int k = t + i * WG;
-            if (k < WN) win[pidx<J>(k)] = make_float4(v[i].x, v[i].y, sqrtf(v[i].x * v[i].x + v[i].y * v[i].y), 0.f);
+            if (k < WN) {
+              const int q = pidx<J>(k);
+              wre[q] = v[i].x;
+              wim[q] = v[i].y;
+              wrr[q] = sqrtf(v[i].x * v[i].x + v[i].y * v[i].y);
+            }
           }
         }
         const float2 *tb = d.taps + (size_t)bank * d.Kmax * d.Lmax;
@@ -232,7 +242,7 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
           it_next = s_next[par ^ 1u];
           prefetch(it_next);   // in flight during the compute below
         }
-        horner_dispatch<J>(KH, win, coef, Lpad, L, t, accr, acci);
+        horner_dispatch<J>(KH, wre, wim, wrr, coef, Lpad, L, t, accr, acci);
       }
 #pragma unroll
       for (int j = 0; j < J; ++j) {
