@@ -19,11 +19,11 @@
 // 5, odd, so the lanes of a read fall in distinct banks), and every window
 // and coefficient read of a chunk is a constant offset from one base.  At
 // 12 bytes per window sample the J = 8, 256-thread kernel needs 33.6 KB of
-// LDS, so four workgroups fit on a CU, as many as its registers allow.  Window positions before the frame come from
-// the frame's halo (the stream's past samples), positions after the frame
-// are zero.  Each lane computes J consecutive outputs from a register window
-// of 2J-1 samples per chunk of J taps; the tap coefficients of the chunk are
-// LDS broadcasts.
+// LDS, so four workgroups fit on a CU, as many as its registers allow.
+// Window positions before the frame come from the frame's halo (the stream's
+// past samples), positions after the frame are zero.  Each lane computes J
+// consecutive outputs from a register window of 2J-1 samples per chunk of J
+// taps; the tap coefficients of the chunk are LDS broadcasts.
 #include <hip/hip_ext.h>
 
 #include "prune_internal.h"
