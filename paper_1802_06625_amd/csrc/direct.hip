@@ -200,6 +200,7 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
   hipStream_t s = (hipStream_t)stream;
   launch_direct_prep(*desc, (const float2 *)x, (const float2 *)taps, (const prune_fb_frame *)frames,
                      (float2 *)y, tile, sc->desc, sc->items, sc->ctr, sc->ctr + 1, sc->ctr + 2, s);
+  // four workgroups per CU, the residency of the J = 8, 256-thread forward kernels
   const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 4, items);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timing_on() && !g_tuning;
