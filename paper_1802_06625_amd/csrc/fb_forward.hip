@@ -93,6 +93,7 @@ __device__ __forceinline__ void horner_dispatch(int KH, const float *wre, const 
                                                 const float *wrr, const float2 *coef, int Lpad,
                                                 int L, int t, float *accr, float *acci) {
   switch (KH) {
+    case 0: break;
     case 1: horner_pass<1, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
     case 2: horner_pass<2, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
     case 3: horner_pass<3, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
@@ -242,7 +243,11 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
           it_next = s_next[par ^ 1u];
           prefetch(it_next);   // in flight during the compute below
         }
-        horner_dispatch<J>(KH, wre, wim, wrr, coef, Lpad, L, t, accr, acci);
+        // a wave whose outputs all lie beyond the frame's end (the last tile
+        // of a frame) stores nothing and skips the arithmetic (KH 0); the
+        // condition is uniform across the wave
+        horner_dispatch<J>(n0 + (t & ~63) * J < n ? KH : 0, wre, wim, wrr, coef, Lpad, L, t, accr,
+                           acci);
       }
 #pragma unroll
       for (int j = 0; j < J; ++j) {
