@@ -20,9 +20,13 @@ design notes):
 * Scheduling: round-robin over actors in creation order, each actor fires at
   most once per sweep; a dynamic actor peeks its control token, decodes it,
   checks availability of the decoded rates, and only then consumes it.
-* Termination: the run ends when no actor can fire; it is a deadlock when
-  external input is still pending or a dynamic actor holds a control token
-  it cannot act on.
+* Termination: the run ends when no actor can fire.  It is a normal end
+  when every actor that cannot fire waits, through a chain of blocking reads,
+  on a source or configuration actor whose external input is used up; it is
+  a deadlock when some actor waits in a cycle or behind a FIFO that is never
+  drained, or when a dynamic actor waits on data its linked partner's firing
+  of the same control token did not send (linked DRPs set differently,
+  Sec. V).
 
 Parity: pinned by tests/test_oracle_moc.py (the Fig. 6 worked example, Eq. 2
 in both cases, Eq. 1 and the control-table example, the Fig. 1 rates, token
@@ -702,18 +706,108 @@ class Graph:
         return total
 
     def _check_termination(self):
-        # With finite input a run always stops; it is stuck (rather than out of
-        # input) when external input is still pending, or when a dynamic actor
-        # holds a control token yet cannot fire: it waits on data that no
-        # firing will produce (the linked-DRP deadlock of Sec. V).  Tokens
-        # left behind by delays are a normal end.
-        pending = [a.id for a in self.actors if a.kind in (SOURCE, CONFIG) and a.state["queue"]]
-        stalled = [a.id for a in self.actors if a.kind not in (SOURCE, CONFIG)
-                   and self.cport(a.id) is not None
-                   and self.fstate[self.cport(a.id).fifos[0]].can_read()]
-        if pending or stalled:
-            raise PruneError(E_DEADLOCK, f"no actor can fire; pending inputs {pending}, "
-                                         f"dynamic actors holding control tokens {stalled}")
+        stuck, linked = self.stop_classification()
+        if stuck or linked:
+            raise PruneError(E_DEADLOCK, f"no actor can fire; actors waiting in a cycle or behind "
+                                         f"a FIFO that is never drained {stuck}, dynamic actors "
+                                         f"waiting on a firing their linked partner has passed {linked}")
+
+    # ---- end of a finite run: wait-for classification ------------------------
+    def _waits(self, aid):
+        """What an actor that cannot fire is missing, as (fifo, 'read'|'write')
+        pairs: a blocking read stalls on an input FIFO holding less than a
+        block, a blocking write on an output FIFO without room for one
+        (Sec. III-A).  A dynamic actor without a control token waits on its
+        control FIFO; with one, on the FIFOs of the ports its token sets
+        active (Eq. 1).  Returns None for a source or configuration actor
+        whose external input is used up, and [] for an actor that can fire."""
+        a = self.actors[aid]
+        fs = self.fstate
+        if a.kind in (SOURCE, CONFIG) and not a.state["queue"]:
+            return None
+        bits = {}
+        cp = self.cport(aid)
+        if cp is not None:
+            if not fs[cp.fifos[0]].can_read():
+                return [(cp.fifos[0], "read")]
+            bits = self._decode(a)[2]
+        waits = []
+        for p in self._ports(aid):
+            if p.kind == CPORT or (p.kind == DRP and not bits[p.id]):
+                continue
+            if p.dir == IN:
+                if not fs[p.fifos[0]].can_read():
+                    waits.append((p.fifos[0], "read"))
+            else:
+                waits.extend((f, "write") for f in p.fifos if not fs[f].can_write())
+        return waits
+
+    def stop_classification(self):
+        """Classify a state in which no actor can fire.
+
+        Returns (stuck, linked): two lists of actor ids; both empty means a
+        normal end of a finite run.
+        * Starvation: a source or configuration actor with no external input
+          left is exhausted.  An actor is starved when one of the FIFOs it
+          waits on has, at its other end, an exhausted or starved actor (the
+          writer for a read, the reader for a write): it stops because some
+          external input ran out, and more of that input would move it.
+          Every other actor that cannot fire is stuck: its waits only lead
+          round a cycle (each waits on what the next has not read or
+          written), which no external input can break.
+        * Linked DRPs (Sec. V): a dynamic actor y that holds a control token
+          and waits to read an active DRP input is followed upstream, through
+          the read waits of the actors feeding it, to the dynamic actor x
+          whose DRP output starts that chain.  In a valid DPG the k-th token
+          of x and of y set the same DCs active, so y's k-th firing can lack
+          data from x only while x has not fired its k-th firing; if x has
+          (counting each actor's firings from its first non-delay control
+          token), the two were set differently and y waits forever.
+        """
+        waits = {a.id: self._waits(a.id) for a in self.actors}
+        writer = {fid: self.ports[s].actor for fid, (s, d, r, q) in enumerate(self.fifos)}
+        reader = {fid: self.ports[d].actor for fid, (s, d, r, q) in enumerate(self.fifos)}
+        starved = {aid for aid, w in waits.items() if w is None}
+        grown = True
+        while grown:
+            grown = False
+            for aid, w in waits.items():
+                if aid in starved or not w:
+                    continue
+                if any((writer[f] if d == "read" else reader[f]) in starved for f, d in w):
+                    starved.add(aid)
+                    grown = True
+        stuck = sorted(aid for aid in waits if aid not in starved)
+
+        def token_index(aid):
+            # firings counted from the first control token that is not a delay
+            return self.actors[aid].firings - self.fifos[self.cport(aid).fifos[0]][3]
+
+        linked = []
+        for y in self.actors:
+            cp = self.cport(y.id)
+            w = waits[y.id]
+            if cp is None or not w or not self.fstate[cp.fifos[0]].can_read():
+                continue
+            drp_in = {p.fifos[0] for p in self._ports(y.id, IN, DRP)}
+            todo = [f for f, d in w if d == "read" and f in drp_in]
+            seen = set()
+            while todo:
+                f = todo.pop()
+                sp = self.ports[self.fifos[f][0]]
+                if sp.kind == DRP:
+                    x = sp.actor
+                    if self.cport(x) is not None and token_index(x) > token_index(y.id):
+                        linked.append(y.id)
+                        break
+                    continue
+                if sp.actor in seen:
+                    continue
+                seen.add(sp.actor)
+                cw = self.cport(sp.actor)
+                cf = cw.fifos[0] if cw is not None else None
+                todo.extend(g for g, d in (waits[sp.actor] or []) if d == "read" and g != cf)
+        return stuck, linked
 
     # ---- results -------------------------------------------------------------
     def sink_output(self, aid):

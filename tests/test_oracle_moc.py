@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+import stopcases
 from oracle import moc
 from oracle.moc import (Graph, PruneError, IN, OUT, SRP, DRP, CPORT, SOURCE, CONFIG,
                         FILTERBANK, SWITCH, SELECT, PASSTHROUGH, SINK)
@@ -370,6 +371,53 @@ def test_mismatched_control_streams_deadlock():
     with pytest.raises(PruneError) as e:
         g.run()
     assert e.value.code == moc.E_DEADLOCK
+
+
+# ---------------------------------------------------------------- end of a finite run
+@pytest.mark.parametrize("name", sorted(stopcases.cases()))
+def test_stop_classification(name):
+    """Wait-for classification of the stop (blocking reads and writes,
+    Sec. III-A; linked DRPs, Sec. V): a normal end iff every actor that cannot
+    fire waits, through the FIFOs it blocks on, on external input that ran
+    out."""
+    d = stopcases.cases()[name]
+    status, g = stopcases.run_oracle(d)
+    assert status == d.expect
+    for f in g.fstate:
+        assert f.max_occ <= f.capacity
+        assert f.occupancy == f.Q + f.tokens_written - f.tokens_read
+
+
+def test_undelayed_cycle_stalls_with_input_unread():
+    """THRES needs MED's previous output and MED needs THRES's: nothing fires,
+    both frames stay in THRES's input FIFO, the sink gets nothing."""
+    d = stopcases.thres_med_cycle(0, 2)
+    status, g = stopcases.run_oracle(d)
+    assert status == "deadlock"
+    stuck, linked = g.stop_classification()
+    assert stuck == [d.names["thres"], d.names["med"], d.names["snk"]] and linked == []
+    assert g.fstate[0].occupancy == 2 * 64
+    assert len(g.sink_output(d.names["snk"])) == 0
+
+
+def test_delayed_cycle_runs_every_frame():
+    """The one-frame delay on MED -> THRES breaks the cycle (the z^-1 of
+    Sec. III-D): every frame reaches the sink and the delayed FIFO ends
+    holding one frame, its delay."""
+    d = stopcases.thres_med_cycle(1, 4)
+    status, g = stopcases.run_oracle(d)
+    assert status == "normal"
+    assert len(g.sink_output(d.names["snk"])) == 4 * 64
+    assert g.fstate[2].occupancy == 64
+
+
+def test_mismatched_tokens_flag_the_select():
+    """Sec. V: x routes its first frame to a1 while y's first token demands
+    a2; x has fired the firing linked to y's, so y is reported."""
+    d = stopcases.switch_select([0], [1], 1)
+    status, g = stopcases.run_oracle(d)
+    stuck, linked = g.stop_classification()
+    assert status == "deadlock" and stuck == [] and linked == [d.names["y"]]
 
 
 # ---------------------------------------------------------------- frame-split invariance
