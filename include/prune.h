@@ -63,7 +63,7 @@ enum {
   PRUNE_E_TOKEN = -8,         /* control value with elements beyond its
                                  declared size, rate outside 1..atr, block
                                  count differing from the firing's rate      */
-  PRUNE_E_DEADLOCK = -9,      /* no actor can fire while input is pending    */
+  PRUNE_E_DEADLOCK = -9,      /* stopped by a cycle of waits (Sec. III-A, V) */
   PRUNE_E_CAPACITY = -10,     /* bound storage smaller than Eq. 2's capacity */
   PRUNE_E_HIP = -11,          /* HIP runtime error (text in last_error)      */
   PRUNE_E_UNSUPPORTED = -12,  /* shape beyond the kernels' limits            */
@@ -423,7 +423,9 @@ prune_status prune_source_push(prune_graph_t g, prune_id src, const void *dev_sa
                                const uint32_t *host_counts, uint32_t n_frames);
 
 /* Queue n_frames firings of configuration actor `cfg` with host side-info
- * (same ring rule as prune_source_push). */
+ * (same ring rule as prune_source_push).  E_TOKEN, with nothing queued, for
+ * a record whose branches lie beyond the bank: K > Kmax in prefix mode, a
+ * branch set with bits at or above Kmax in mask mode. */
 prune_status prune_config_push(prune_graph_t g, prune_id cfg, const prune_side_info *host_side,
                                uint32_t n_frames, prune_stream_t stream);
 
@@ -443,8 +445,17 @@ prune_status prune_sink_bind_output(prune_graph_t g, prune_id snk, void *dev_out
  * in the iteration) in batches as large as the pending input, the FIFO
  * capacities and max_firings (read as a cap on iterations per batch, 0 =
  * none) allow.  *fired (may be NULL) receives firings (PER_FIRING) or
- * iterations (BATCHED).  E_DEADLOCK if nothing can fire while input is
- * pending; E_UNSUPPORTED for batched mode on graphs with delays or cycles. */
+ * iterations (BATCHED).  When PER_FIRING stops because nothing can fire, the
+ * stop is classified by what each actor waits for (blocking reads and
+ * writes, Sec. III-A): PRUNE_OK when every actor that cannot fire waits,
+ * through the FIFOs it blocks on, on a source or configuration actor whose
+ * pushed input is used up (more input may be pushed and fired later);
+ * E_DEADLOCK when some actor's waits only lead round a cycle, or when a
+ * dynamic actor waits on data that its linked partner's firing of the same
+ * control-token index did not send (linked DRPs set differently, Sec. V).
+ * The firings issued before the stop stay queued on `stream` either way.
+ * E_UNSUPPORTED for batched mode on graphs with cycles or delays that are
+ * not whole blocks. */
 prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings,
                               prune_stream_t stream, uint64_t *fired);
 
@@ -507,6 +518,7 @@ typedef struct {
  * E_UNSUPPORTED beyond the limits, E_ARG on inconsistent descriptors. */
 prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const void *taps,
                               const void *frames, void *y, prune_stream_t stream);
+
 
 /* Validate a device frame table against `desc` (synchronous on `stream`):
  * *n_bad = number of frames with a stream index >= n_streams, t0 + n beyond

@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include "prune.h"
+#include "prune_rules.h"
 
 namespace prune {
 
@@ -24,75 +25,6 @@ enum : uint32_t {
   kErrCount = 4u,      // block count differs from the firing's rate
   kErrTrace = 8u,      // trace buffer overflow
 };
-
-// ---------------------------------------------------------------- Eq. 2
-__host__ __device__ inline uint64_t fifo_capacity(uint32_t r, uint32_t Q, uint32_t C) {
-  return (Q % r) ? (uint64_t)r * C + Q
-                 : ((uint64_t)r * C > Q ? (uint64_t)r * C : (uint64_t)Q);
-}
-
-// ---------------------------------------------------------------- Fig. 6 rule
-// Aligned (Q mod r == 0): ring of max(rC, Q) slots in blocks of r, Q/r blocks
-// prefilled; write j -> block (Q/r + j) mod blocks, read i -> block i mod blocks.
-// Unaligned: ring of rC slots plus a Q-slot overflow area; write j at
-// Q + (j mod C) r (copied back to slot 0 when it runs past rC-1), read i at
-// (i mod C) r.
-__host__ __device__ inline uint64_t fifo_write_slot(uint32_t r, uint32_t Q, uint32_t C,
-                                                     uint64_t j) {
-  if (Q % r == 0) {
-    uint64_t blocks = fifo_capacity(r, Q, C) / r;
-    return ((Q / r + j) % blocks) * r;
-  }
-  return Q + (j % C) * (uint64_t)r;
-}
-
-__host__ __device__ inline uint64_t fifo_read_slot(uint32_t r, uint32_t Q, uint32_t C,
-                                                    uint64_t i) {
-  if (Q % r == 0) {
-    uint64_t blocks = fifo_capacity(r, Q, C) / r;
-    return (i % blocks) * r;
-  }
-  return (i % C) * (uint64_t)r;
-}
-
-// Blocking rules in terms of blocks in flight (writes - reads).
-__host__ __device__ inline bool fifo_can_write(uint32_t r, uint32_t Q, uint32_t C,
-                                               int64_t inflight) {
-  if (Q % r == 0) return (int64_t)(Q / r) + inflight < (int64_t)(fifo_capacity(r, Q, C) / r);
-  return (inflight + 1) * (int64_t)r <= (int64_t)r * C - (int64_t)Q;
-}
-
-__host__ __device__ inline bool fifo_can_read(uint32_t r, uint32_t Q, uint32_t /*C*/,
-                                              int64_t inflight) {
-  if (Q % r == 0) return (int64_t)(Q / r) + inflight > 0;
-  return (int64_t)Q + inflight * (int64_t)r >= (int64_t)r;
-}
-
-// ---------------------------------------------------------------- Eq. 1
-// tokrate(p, phi) = BTOI(v_phi[T[j][p]]) * atr(p): the element's bit.
-__host__ __device__ inline uint32_t decode_bit(uint32_t mask, uint32_t element) {
-  return element ? (mask >> (element - 1)) & 1u : 0u;
-}
-
-// Configuration actor mapping: external side-information -> control token.
-__host__ __device__ inline prune_ctrl_token config_map(uint32_t mode, uint32_t Kmax,
-                                                       prune_side_info s) {
-  prune_ctrl_token t;
-  if (mode == PRUNE_CONFIG_ROUTE) {
-    t.mask = s.route < 32 ? (1u << s.route) : 0u;
-  } else if (mode == PRUNE_CONFIG_MASK) {
-    const uint32_t bank_bits = Kmax >= 32 ? 0xffffffffu : ((1u << Kmax) - 1u);
-    const uint32_t sh = s.bank * Kmax;
-    t.mask = sh < 32 ? ((s.K & bank_bits) << sh) : 0u;
-  } else {
-    uint32_t K = s.K > 31 ? 31 : s.K;
-    uint32_t m = K ? ((K >= 32) ? 0xffffffffu : ((1u << K) - 1u)) : 0u;
-    uint32_t sh = s.bank * Kmax;
-    t.mask = sh < 32 ? (m << sh) : 0u;
-  }
-  t.rate = s.n;
-  return t;
-}
 
 // ---------------------------------------------------------------- device tables
 struct FifoDev {

@@ -19,6 +19,7 @@
 
 #include "prune.h"
 #include "design_analysis.h"
+#include "stop_rules.h"
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
@@ -845,6 +846,57 @@ bool can_fire(prune_graph *g, uint32_t aid) {
   return true;
 }
 
+// ---------------------------------------------------------------- end of a run
+// A per-firing run stopped (nothing can fire): classify the stop on a plain
+// view of the graph's host state (stop_rules.cpp).  A normal end returns
+// PRUNE_OK; actors stuck round a cycle of waits, or dynamic actors waiting on
+// data their linked partner's firing did not send, give PRUNE_E_DEADLOCK.
+prune_status classify_stop(prune_graph *g) {
+  std::vector<StopActor> va(g->actors.size());
+  std::vector<StopPort> vp(g->ports.size());
+  std::vector<StopFifo> vf(g->fifos.size());
+  for (uint32_t f = 0; f < g->fifos.size(); ++f) {
+    const HFifo &F = g->fifos[f];
+    vf[f] = {F.src, F.dst, F.rate, F.delay, F.inflight};
+  }
+  for (uint32_t p = 0; p < g->ports.size(); ++p) {
+    const HPort &P = g->ports[p];
+    vp[p].actor = P.actor;
+    vp[p].dir = P.dir;
+    vp[p].kind = P.kind;
+    vp[p].fifos = P.fifos;
+    vp[p].element = 0;
+    if (P.kind == PRUNE_DRP && !P.internal) {
+      auto it = g->table.find({controller_port(g, g->actors[P.actor]), p});
+      if (it != g->table.end()) vp[p].element = it->second;
+    }
+  }
+  for (uint32_t a = 0; a < g->actors.size(); ++a) {
+    const HActor &A = g->actors[a];
+    StopActor &V = va[a];
+    V.kind = A.kind;
+    V.exhausted = (A.kind == PRUNE_SOURCE && A.src_q.empty()) || (A.kind == PRUNE_CONFIG && A.side_q.empty());
+    V.cport_fifo = cport_fifo(g, A);
+    V.has_token = V.cport_fifo >= 0 && !g->fifos[V.cport_fifo].mirror.empty();
+    V.token_mask = V.has_token ? g->fifos[V.cport_fifo].mirror.front().mask : 0u;
+    V.firings = A.firings;
+    V.ports = A.ports;
+  }
+  const StopResult r = classify_stop_view(va, vp, vf, g->C);
+  if (r.stuck.empty() && r.linked.empty()) return PRUNE_OK;
+  std::string msg = "no actor can fire;";
+  if (!r.stuck.empty()) {
+    msg += " actors waiting round a cycle:";
+    for (uint32_t a : r.stuck) msg += " " + std::to_string(a);
+    msg += ";";
+  }
+  if (!r.linked.empty()) {
+    msg += " dynamic actors waiting on data their linked partner's firing did not send:";
+    for (uint32_t a : r.linked) msg += " " + std::to_string(a);
+  }
+  return fail(PRUNE_E_DEADLOCK, msg);
+}
+
 prune_status fire_one(prune_graph *g, uint32_t aid, hipStream_t s) {
   HActor &A = g->actors[aid];
   const prune_ctrl_token *tok = nullptr;
@@ -1464,6 +1516,14 @@ prune_status prune_config_push(prune_graph_t g, prune_id cfg, const prune_side_i
   if (cfg >= g->actors.size() || g->actors[cfg].kind != PRUNE_CONFIG || (!side && n))
     return fail(PRUNE_E_ARG, "not a configuration actor");
   HActor &A = g->actors[cfg];
+  // side-information that addresses branches beyond a bank (the same records
+  // the oracle's configuration actor rejects)
+  for (uint32_t f = 0; f < n; ++f) {
+    if (A.cfg.mode == PRUNE_CONFIG_PREFIX && side[f].K > A.cfg.Kmax)
+      return fail(PRUNE_E_TOKEN, "record " + std::to_string(f) + ": K above the bank size");
+    if (A.cfg.mode == PRUNE_CONFIG_MASK && A.cfg.Kmax < 32 && (side[f].K >> A.cfg.Kmax))
+      return fail(PRUNE_E_TOKEN, "record " + std::to_string(f) + ": branch set beyond the bank size");
+  }
   TRY(ensure_ring(g, A, sizeof(prune_side_info), n));
   TRY(ring_write(A, sizeof(prune_side_info), side, n));
   TRY(sync_actor_dev(g, cfg));
@@ -1507,18 +1567,7 @@ prune_status prune_graph_fire(prune_graph_t g, int mode, uint32_t max_firings, p
     }
     HIPCHECK(hipGetLastError());
     if (fired) *fired = done;
-    if (!max_firings || done < max_firings) {
-      bool all_pending = false, some = false;
-      for (auto &A : g->actors) {
-        if (A.kind == PRUNE_SOURCE || A.kind == PRUNE_CONFIG) {
-          const bool pend = A.kind == PRUNE_SOURCE ? !A.src_q.empty() : !A.side_q.empty();
-          if (!some) all_pending = true;
-          some = true;
-          all_pending = all_pending && pend;
-        }
-      }
-      if (some && all_pending) return fail(PRUNE_E_DEADLOCK, "no actor can fire while every input is pending");
-    }
+    if (!max_firings || done < max_firings) return classify_stop(g);
     return PRUNE_OK;
   }
   if (mode != PRUNE_BATCHED && mode != PRUNE_BATCHED_GRAPH) return fail(PRUNE_E_ARG, "unknown mode");
