@@ -268,3 +268,90 @@ def test_backward_optional_gradients(form):
         assert torch.equal(gt_only, gt_full)
     _, rt = fb_stream_adjoint(wl.x[0], stream_frames(wl, 0), wl.taps[0], wl.bank_L, wl.Kmax, wl.gy[0])
     assert rel_l2(gt_only.cpu().numpy()[0], rt) <= TOL
+
+
+# ---------------------------------------------------------------- measured sizes
+def _gh_run(n_items_max):
+    """Tiles per run of the matrix-core grad_h kernel: up to 8, about one run
+    per workgroup of its grid of two workgroups per compute unit."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    return max(1, min(8, n_items_max // (2 * ncu)))
+
+
+@pytest.mark.parametrize("form", BWD_FORMS)
+def test_backward_full_c4(form):
+    """The differentiation workload at its full size (256 x 8192, K = 8,
+    L = 16): the grad_h kernel takes runs of several tiles, the grad_x and
+    vector kernels loop over tickets and grid strides."""
+    announce(f"backward full C4 form {form}")
+    wl = synth.make("C4", cotangent=True)
+    rows = _rows(wl)
+    mfl = int(wl.side[:, :, 1].max())
+    assert _gh_run(len(rows) * ((mfl + 1023) // 1024)) >= 4
+    gx, gt = _backward(torch.from_numpy(wl.x).cuda(), torch.from_numpy(wl.taps).cuda(),
+                       ops.frame_table(rows), torch.from_numpy(wl.gy).cuda(), wl.Kmax, wl.bank_L, mfl,
+                       form)
+    rx, rt = fb_stream_adjoint(wl.x[0], stream_frames(wl, 0), wl.taps[0], wl.bank_L, wl.Kmax, wl.gy[0])
+    assert rel_l2(gx[0], rx) <= TOL, rel_l2(gx[0], rx)
+    assert rel_l2(gt[0], rt) <= TOL, rel_l2(gt[0], rt)
+
+
+@pytest.mark.parametrize("form", BWD_FORMS)
+def test_backward_full_c5_sampled_streams(form):
+    """The wide workload at full size (64 streams x 16 x 32768, K = 7,
+    L = 64, about 30 % passthrough frames): every stream's frames in the
+    table, as the bench runs it; eight streams checked against the oracle."""
+    announce(f"backward full C5 form {form}")
+    wl = synth.make("C5", cotangent=True)
+    rows = ops.frames_from_side(wl.side, wl.Kmax, True)
+    mfl = int(wl.side[:, :, 1].max())
+    assert _gh_run(len(rows) * ((mfl + 1023) // 1024)) == 8
+    gx, gt = _backward(torch.from_numpy(wl.x).cuda(), torch.from_numpy(wl.taps).cuda(),
+                       ops.frame_table(rows), torch.from_numpy(wl.gy).cuda(), wl.Kmax, wl.bank_L, mfl,
+                       form)
+    for s in (0, 9, 18, 27, 36, 45, 54, 63):
+        ref = [(t0, n, m, r) for (ss, t0, n, m, r) in rows if ss == s]
+        rx, rt = fb_stream_adjoint(wl.x[s], ref, wl.taps[s], wl.bank_L, wl.Kmax, wl.gy[s])
+        assert rel_l2(gx[s], rx) <= TOL, (s, rel_l2(gx[s], rx))
+        assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
+
+
+@pytest.mark.parametrize("form", BWD_FORMS)
+@pytest.mark.parametrize("run", [2, 3, 7])
+def test_backward_tile_runs(run, form):
+    """Frame tables sized so the grad_h kernel takes runs of 2, 3 and 7 tiles:
+    ragged frame lengths (tiles ending inside frames, frames shorter than a
+    tile), arbitrary branch masks over two banks, passthrough frames, and
+    fewer tiles than the table's bound, on two streams."""
+    announce(f"backward tile runs run={run} form {form}")
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    mfl = 8192
+    n_frames = run * 2 * ncu // 8 + 1
+    assert _gh_run(n_frames * 8) == run
+    rng = np.random.default_rng(500 + run)
+    Kmax, bank_L = 6, (16, 33)
+    D = Kmax * len(bank_L)
+    S = 2
+    rows, N = [], 0
+    for f in range(n_frames):
+        s = f % S
+        n = int(rng.integers(1, mfl + 1)) if rng.random() < 0.7 else mfl
+        rows.append([s, 0, n, int(rng.integers(0, 1 << D)), int(rng.random() < 0.1)])
+    t = [0] * S
+    for r_ in rows:
+        r_[1] = t[r_[0]]
+        t[r_[0]] += r_[2] + (int(rng.integers(0, 40)) if rng.random() < 0.3 else 0)
+    rows = sorted(tuple(r_) for r_ in rows)       # by stream, then t0
+    N = max(t)
+    taps = ((rng.standard_normal((S, 2, Kmax, 33)) + 1j * rng.standard_normal((S, 2, Kmax, 33)))
+            / 64).astype(np.complex64)
+    taps[:, 0, :, 16:] = 0
+    x = ((rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))) * 0.3).astype(np.complex64)
+    gy = (rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))).astype(np.complex64)
+    gx, gt = _backward(torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(), ops.frame_table(rows),
+                       torch.from_numpy(gy).cuda(), Kmax, bank_L, mfl, form)
+    for s in range(S):
+        ref = [(t0, n, m, r) for (ss, t0, n, m, r) in rows if ss == s]
+        rx, rt = fb_stream_adjoint(x[s], ref, taps[s], bank_L, Kmax, gy[s])
+        assert rel_l2(gx[s], rx) <= TOL, (s, rel_l2(gx[s], rx))
+        assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
