@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--only-c2", action="store_true", help="skip the other workloads")
     p.add_argument("--only", default="", help="run one secondary workload only: c3, c4, c4fit, c5, c5bwd, c2u, paper, host, motion")
+    p.add_argument("--ceilings", action="store_true",
+                   help="only the ceiling probes (copy bandwidth, unpacked fp32 FMA, fp32 MFMA)")
     p.add_argument("--copy-calib", action="store_true",
                    help="only copy a 1 GiB buffer twice (HBM counter calibration)")
     p.add_argument("--profile-only", action="store_true",
@@ -62,6 +64,46 @@ def measured_traffic(kernel_src, record):
         return float(kv["traffic_bytes"]) if kv.get("source_sha256_16") == h else None
     except OSError:
         return None
+
+
+def measure_ceilings(sweep=False):
+    """The device's sustained copy bandwidth, unpacked fp32 FMA rate and fp32
+    matrix-core rate (prune_probe_ceiling), with the shader clock measured
+    during each, beside the datasheet peaks."""
+    import ctypes as C
+    from paper_1802_06625_amd import _lib as L
+
+    def probe(kind, waves, size, reps):
+        r = L.ProbeResult()
+        L.call("prune_probe_ceiling", kind, waves, size, reps, C.byref(r))
+        return r
+
+    out = {}
+    r = probe(L.PROBE_COPY, 0, 1 << 30, 10)
+    out["copy"] = {"gbps": round(r.rate / 1e9, 1), "bytes_per_launch": r.work,
+                   "clock_ghz": round(r.clock_ghz, 3), "datasheet_gbps": PEAK_HBM_GBPS,
+                   "frac_of_datasheet": round(r.rate / 1e9 / PEAK_HBM_GBPS, 4)}
+    fma = {}
+    for w in ((1, 2, 4, 8) if sweep else (2, 8)):
+        r = probe(L.PROBE_FMA32, w, 4096, 5)
+        per_cu_cycle = r.rate / (r.n_cu * r.clock_ghz * 1e9) / 64.0 if r.clock_ghz else None
+        fma[w] = {"tflops": round(2 * r.rate / 1e12, 2), "clock_ghz": round(r.clock_ghz, 3),
+                  "wave64_fma_per_cu_per_cycle": round(per_cu_cycle, 3) if per_cu_cycle else None}
+    best = max(fma, key=lambda w: fma[w]["tflops"])
+    out["fma32_unpacked"] = {"by_waves_per_simd": {str(k): v for k, v in fma.items()},
+                             "tflops": fma[best]["tflops"], "clock_ghz": fma[best]["clock_ghz"],
+                             "wave64_fma_per_cu_per_cycle": fma[best]["wave64_fma_per_cu_per_cycle"],
+                             "datasheet_tflops_packed": PEAK_FP32_VECTOR_TFLOPS,
+                             "datasheet_tflops_unpacked": PEAK_FP32_VECTOR_TFLOPS / 2}
+    mf = {}
+    for w in ((1, 2, 4) if sweep else (2,)):
+        r = probe(L.PROBE_MFMA32, w, 2048, 5)
+        mf[w] = {"tflops": round(r.rate / 1e12, 2), "clock_ghz": round(r.clock_ghz, 3)}
+    best = max(mf, key=lambda w: mf[w]["tflops"])
+    out["mfma32"] = {"by_waves_per_simd": {str(k): v for k, v in mf.items()},
+                     "tflops": mf[best]["tflops"], "clock_ghz": mf[best]["clock_ghz"],
+                     "datasheet_tflops": PEAK_FP32_MATRIX_TFLOPS}
+    return out
 
 
 def algorithmic_flops(side, L):
@@ -138,6 +180,9 @@ def main():
               "host": lambda: bench_host_stream(),
               "motion": lambda: bench_motion(min(args.steps, 10), min(args.warmup, 5))}[args.only]
         print(json.dumps({args.only: fn()}))
+        return
+    if args.ceilings:
+        print(json.dumps({"ceilings": measure_ceilings(sweep=True)}))
         return
     if args.copy_calib:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")

@@ -585,6 +585,31 @@ prune_status prune_last_fb_kernel_ms(float *ms, uint32_t *launches);
  * of a fire call's work.  Process-wide; takes effect at the next batch. */
 prune_status prune_set_batch_pipeline(int on);
 
+/* ---- ceiling probes (measurement, not an operation of the paper) --------- */
+/* The rooflines the kernels are compared against, measured on the device
+ * the library runs on instead of taken from its datasheet.
+ *  COPY   float4 grid-stride copy between two device buffers of `size` bytes
+ *         each; work = bytes read + written (HBM bandwidth).
+ *  FMA32  8 independent chains of unpacked fp32 FMAs per lane, `waves`
+ *         waves (1..8) per SIMD, `size` trips of 64 FMAs; work = FMAs.
+ *  MFMA32 4 independent 16x16x4 fp32 matrix-core chains per wave, `waves`
+ *         waves per SIMD, `size` trips; work = flops (2048 per instruction).
+ * One warm-up launch, then `reps` launches timed with HIP events on the
+ * null stream.  The clock is the shader clock the launches ran at: core
+ * cycles over real-time ticks read by each workgroup at its start and end.
+ * The probe allocates and frees its own buffers.  E_ARG for sizes or wave
+ * counts out of range, E_HIP when an allocation or launch fails. */
+enum { PRUNE_PROBE_COPY = 0, PRUNE_PROBE_FMA32 = 1, PRUNE_PROBE_MFMA32 = 2 };
+typedef struct {
+  double seconds;     /* per launch */
+  double work;        /* per launch: bytes, FMAs or flops */
+  double rate;        /* work per second */
+  double clock_ghz;   /* measured shader clock */
+  uint32_t grid, block, n_cu, pad;
+} prune_probe_result;
+prune_status prune_probe_ceiling(int kind, uint32_t waves, uint64_t size, uint32_t reps,
+                                 prune_probe_result *out);
+
 /* ---- host evaluation of the integer rules -------------------------------- */
 /* The kernels' integer rules compiled for the host from the same source:
  * Eq. 2 capacity (tokens), the first slots of writes and reads 0..n-1 of a

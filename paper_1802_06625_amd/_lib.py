@@ -64,6 +64,15 @@ class TraceRecord(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in ("type", "a", "b", "c", "d", "e", "f", "pad")]
 
 
+class ProbeResult(C.Structure):
+    _fields_ = [("seconds", C.c_double), ("work", C.c_double), ("rate", C.c_double),
+                ("clock_ghz", C.c_double), ("grid", C.c_uint32), ("block", C.c_uint32),
+                ("n_cu", C.c_uint32), ("pad", C.c_uint32)]
+
+
+PROBE_COPY, PROBE_FMA32, PROBE_MFMA32 = 0, 1, 2
+
+
 class FbDesc(C.Structure):
     _fields_ = [("n_streams", C.c_uint32), ("n_frames", C.c_uint32), ("stream_len", C.c_uint64),
                 ("n_banks", C.c_uint32), ("Kmax", C.c_uint32), ("L", C.c_uint32 * MAX_BANKS),
@@ -131,6 +140,8 @@ SIGNATURES = [
                                C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("prune_rule_config_token", _ST, [C.c_uint32, C.c_uint32, C.POINTER(SideInfo),
                                       C.POINTER(CtrlToken)]),
+    ("prune_probe_ceiling", _ST, [C.c_int, C.c_uint32, C.c_uint64, C.c_uint32,
+                                  C.POINTER(ProbeResult)]),
     ("prune_status_string", C.c_char_p, [_ST]),
     ("prune_last_error", C.c_char_p, []),
 ]
