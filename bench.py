@@ -79,18 +79,25 @@ def measure_ceilings(sweep=False):
         return r
 
     out = {}
-    r = probe(L.PROBE_COPY, 0, 1 << 30, 10)
-    out["copy"] = {"gbps": round(r.rate / 1e9, 1), "bytes_per_launch": r.work,
-                   "clock_ghz": round(r.clock_ghz, 3), "datasheet_gbps": PEAK_HBM_GBPS,
-                   "frac_of_datasheet": round(r.rate / 1e9 / PEAK_HBM_GBPS, 4)}
+    cp = {}
+    for w in ((4, 8, 16) if sweep else (8,)):
+        r = probe(L.PROBE_COPY, w, 1 << 30, 10)
+        cp[w] = {"gbps": round(r.rate / 1e9, 1), "clock_ghz": round(r.clock_ghz, 3)}
+    best = max(cp, key=lambda w: cp[w]["gbps"])
+    out["copy"] = {"by_workgroups_per_cu": {str(k): v for k, v in cp.items()},
+                   "gbps": cp[best]["gbps"], "bytes_per_launch": 2 * (1 << 30),
+                   "clock_ghz": cp[best]["clock_ghz"], "datasheet_gbps": PEAK_HBM_GBPS,
+                   "frac_of_datasheet": round(cp[best]["gbps"] / PEAK_HBM_GBPS, 4)}
     fma = {}
-    for w in ((1, 2, 4, 8) if sweep else (2, 8)):
-        r = probe(L.PROBE_FMA32, w, 4096, 5)
-        per_cu_cycle = r.rate / (r.n_cu * r.clock_ghz * 1e9) / 64.0 if r.clock_ghz else None
-        fma[w] = {"tflops": round(2 * r.rate / 1e12, 2), "clock_ghz": round(r.clock_ghz, 3),
-                  "wave64_fma_per_cu_per_cycle": round(per_cu_cycle, 3) if per_cu_cycle else None}
+    for form, kind in (("chain", L.PROBE_FMA32), ("accumulate", L.PROBE_FMAC32),
+                       ("chain_vgpr", L.PROBE_FMA3V), ("mixed", L.PROBE_FMAMIX)):
+        for w in ((1, 2, 4, 8) if sweep else (2, 8)):
+            r = probe(kind, w, 4096, 5)
+            per_cu_cycle = r.rate / (r.n_cu * r.clock_ghz * 1e9) / 64.0 if r.clock_ghz else None
+            fma[f"{form}_w{w}"] = {"tflops": round(2 * r.rate / 1e12, 2), "clock_ghz": round(r.clock_ghz, 3),
+                                   "wave64_fma_per_cu_per_cycle": round(per_cu_cycle, 3) if per_cu_cycle else None}
     best = max(fma, key=lambda w: fma[w]["tflops"])
-    out["fma32_unpacked"] = {"by_waves_per_simd": {str(k): v for k, v in fma.items()},
+    out["fma32_unpacked"] = {"by_form_and_waves_per_simd": fma, "best": best,
                              "tflops": fma[best]["tflops"], "clock_ghz": fma[best]["clock_ghz"],
                              "wave64_fma_per_cu_per_cycle": fma[best]["wave64_fma_per_cu_per_cycle"],
                              "datasheet_tflops_packed": PEAK_FP32_VECTOR_TFLOPS,

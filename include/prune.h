@@ -589,9 +589,15 @@ prune_status prune_set_batch_pipeline(int on);
 /* The rooflines the kernels are compared against, measured on the device
  * the library runs on instead of taken from its datasheet.
  *  COPY   float4 grid-stride copy between two device buffers of `size` bytes
- *         each; work = bytes read + written (HBM bandwidth).
+ *         each, `waves` (0..32, 0 = 8) 256-thread workgroups per CU;
+ *         work = bytes read + written (HBM bandwidth).
  *  FMA32  8 independent chains of unpacked fp32 FMAs per lane, `waves`
  *         waves (1..8) per SIMD, `size` trips of 64 FMAs; work = FMAs.
+ *  FMAC32 16 accumulators per lane, acc += a * b with every operand in a
+ *         register, `waves` waves per SIMD, `size` trips of 64 FMAs.
+ *  FMA3V  8 chains v = v * a + b per lane, every operand in a register
+ *         (three-operand encoding), `size` trips of 64 FMAs.
+ *  FMAMIX 4 such chains beside 4 accumulators, `size` trips of 64 FMAs.
  *  MFMA32 4 independent 16x16x4 fp32 matrix-core chains per wave, `waves`
  *         waves per SIMD, `size` trips; work = flops (2048 per instruction).
  * One warm-up launch, then `reps` launches timed with HIP events on the
@@ -599,7 +605,8 @@ prune_status prune_set_batch_pipeline(int on);
  * cycles over real-time ticks read by each workgroup at its start and end.
  * The probe allocates and frees its own buffers.  E_ARG for sizes or wave
  * counts out of range, E_HIP when an allocation or launch fails. */
-enum { PRUNE_PROBE_COPY = 0, PRUNE_PROBE_FMA32 = 1, PRUNE_PROBE_MFMA32 = 2 };
+enum { PRUNE_PROBE_COPY = 0, PRUNE_PROBE_FMA32 = 1, PRUNE_PROBE_MFMA32 = 2, PRUNE_PROBE_FMAC32 = 3,
+       PRUNE_PROBE_FMA3V = 4, PRUNE_PROBE_FMAMIX = 5 };
 typedef struct {
   double seconds;     /* per launch */
   double work;        /* per launch: bytes, FMAs or flops */

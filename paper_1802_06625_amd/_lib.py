@@ -70,7 +70,7 @@ class ProbeResult(C.Structure):
                 ("n_cu", C.c_uint32), ("pad", C.c_uint32)]
 
 
-PROBE_COPY, PROBE_FMA32, PROBE_MFMA32 = 0, 1, 2
+PROBE_COPY, PROBE_FMA32, PROBE_MFMA32, PROBE_FMAC32, PROBE_FMA3V, PROBE_FMAMIX = 0, 1, 2, 3, 4, 5
 
 
 class FbDesc(C.Structure):
