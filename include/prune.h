@@ -519,6 +519,28 @@ typedef struct {
 prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const void *taps,
                               const void *frames, void *y, prune_stream_t stream);
 
+/* prune_fb_forward without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors as
+ * prune_fb_forward.  Its frame descriptors and work list live in a fixed
+ * device array of the library (about 2.9 MB per device, held until the
+ * process ends) instead of library-allocated memory, so:
+ *  - n_frames <= PRUNE_NOALLOC_MAX_FRAMES and n_frames * ceil(max_frame_len
+ *    / tile) <= PRUNE_NOALLOC_MAX_ITEMS (tile: 1024 to 4096 outputs by
+ *    variant), else E_CAPACITY (text in prune_last_error), nothing launched;
+ *  - every call on one device uses the same array: calls that overlap in
+ *    time on one device (different streams or threads) race and must be
+ *    ordered by the caller.  The prep kernel of each call rewrites
+ *    everything the forward kernel reads, so nothing carries over.
+ * It never runs the autotuner (which allocates a trial batch): the variant
+ * is the one set by prune_set_fb_variant, else the one the autotuner has
+ * already chosen in this process for the shape class, else variant 1.
+ * Launches are not timed (prune_timing_enable). */
+#define PRUNE_NOALLOC_MAX_FRAMES 8192
+#define PRUNE_NOALLOC_MAX_ITEMS 262144
+prune_status prune_fb_forward_noalloc(const prune_fb_desc *desc, const void *x, const void *taps,
+                                      const void *frames, void *y, prune_stream_t stream);
+
 
 /* Validate a device frame table against `desc` (synchronous on `stream`):
  * *n_bad = number of frames with a stream index >= n_streams, t0 + n beyond

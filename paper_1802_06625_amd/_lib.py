@@ -122,6 +122,7 @@ SIGNATURES = [
     ("prune_trace_enable", _ST, [_P, C.c_size_t]),
     ("prune_trace_fetch", _ST, [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]),
     ("prune_fb_forward", _ST, [C.POINTER(FbDesc), _P, _P, _P, _P, _P]),
+    ("prune_fb_forward_noalloc", _ST, [C.POINTER(FbDesc), _P, _P, _P, _P, _P]),
     ("prune_fb_workspace_bytes", _ST, [C.POINTER(FbDesc), C.POINTER(C.c_size_t)]),
     ("prune_fb_backward", _ST, [C.POINTER(FbDesc), _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     ("prune_set_fb_variant", _ST, [C.c_int]),

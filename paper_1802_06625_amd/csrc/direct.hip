@@ -162,10 +162,47 @@ int ncu() {
   return g_ncu;
 }
 
+// Fixed workspace of prune_fb_forward_noalloc, one copy per device for the
+// life of the process: frame descriptors, then work items, then the item
+// count, ticket and error word.
+constexpr size_t kNaDescBytes =
+    ((size_t)PRUNE_NOALLOC_MAX_FRAMES * sizeof(FbFrameDesc) + 255) / 256 * 256;
+constexpr size_t kNaItemBytes = (size_t)PRUNE_NOALLOC_MAX_ITEMS * sizeof(WorkItem);
+constexpr size_t kNaBytes = kNaDescBytes + kNaItemBytes + 256;
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+unsigned char *g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of the current device's copy of the workspace, looked up
+// once per device with that device current.  In host code `scratch` names a
+// host-side stand-in, never the device memory, so only this address is
+// passed to kernels.
+unsigned char *noalloc_workspace() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaMaxDevices) {
+    set_last_error("prune_fb_forward_noalloc: no current device, or device index beyond 63");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_last_error("prune_fb_forward_noalloc: hipGetSymbolAddress of the workspace failed");
+      return nullptr;
+    }
+    g_na_ptr[dev] = (unsigned char *)p;
+  }
+  return g_na_ptr[dev];
+}
+
 }  // namespace
 
 namespace prune {
 int choose_variant(uint32_t L, uint32_t K, uint32_t n);
+int cached_variant(uint32_t L, uint32_t K, uint32_t n);
 
 prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, const void *taps,
                                       const void *frames, void *y, int variant,
@@ -230,6 +267,42 @@ prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const vo
   return prune_fb_forward_variant(desc, x, taps, frames, y, v, stream);
 }
 
+prune_status prune_fb_forward_noalloc(const prune_fb_desc *desc, const void *x, const void *taps,
+                                      const void *frames, void *y, prune_stream_t stream) {
+  prune_status st = check_desc(desc);
+  if (st != PRUNE_OK) return st;
+  if (!x || !taps || !frames || !y) return PRUNE_E_ARG;
+  if (desc->n_frames == 0) return PRUNE_OK;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
+  // never the autotuner (it allocates its trial batch): the forced variant,
+  // else this process's choice for the shape class, else the first variant
+  int variant = forced_variant();
+  if (!variant) variant = cached_variant(Lmax, desc->Kmax, desc->max_frame_len);
+  if (!variant) variant = 1;
+  const uint32_t tile = (uint32_t)fb_variant_tile(variant);
+  const size_t per = ((size_t)desc->max_frame_len + tile - 1) / tile;
+  const size_t items = (size_t)desc->n_frames * (per ? per : 1);
+  if (desc->n_frames > PRUNE_NOALLOC_MAX_FRAMES || items > PRUNE_NOALLOC_MAX_ITEMS) {
+    set_last_error("prune_fb_forward_noalloc: more frames or tiles than its fixed workspace holds "
+                   "(PRUNE_NOALLOC_MAX_FRAMES, PRUNE_NOALLOC_MAX_ITEMS)");
+    return PRUNE_E_CAPACITY;
+  }
+  unsigned char *base = noalloc_workspace();
+  if (!base) return PRUNE_E_HIP;
+  FbFrameDesc *fd = (FbFrameDesc *)base;
+  WorkItem *it = (WorkItem *)(base + kNaDescBytes);
+  uint32_t *ctr = (uint32_t *)(base + kNaDescBytes + kNaItemBytes);   // n_items, ticket, err
+  hipStream_t s = (hipStream_t)stream;
+  // the prep kernel writes the item count and clears the ticket before the
+  // forward kernel reads them; the error word is not read on this path
+  launch_direct_prep(*desc, (const float2 *)x, (const float2 *)taps, (const prune_fb_frame *)frames,
+                     (float2 *)y, tile, fd, it, ctr, ctr + 1, ctr + 2, s);
+  const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 4, items);
+  fb_forward_launch(variant, fd, it, ctr, (unsigned int *)(ctr + 1), grid, s);
+  return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
+}
+
 prune_status prune_fb_check_frames(const prune_fb_desc *desc, const void *frames, uint32_t *n_bad,
                                    prune_stream_t stream) {
   if (!desc || !n_bad || (desc->n_frames && !frames)) return PRUNE_E_ARG;
@@ -267,11 +340,21 @@ extern int forced_variant();
 // Time each forward variant on a synthetic batch of the shape class and keep
 // the fastest.  Key: (L, K, frame length class); L is exact because the
 // kernels pad the tap count to different chunk sizes.
+static uint32_t length_class(uint32_t n) { return n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512); }
+
+// The variant the autotuner already chose in this process for the shape
+// class, or 0; never tunes.
+int cached_variant(uint32_t L, uint32_t K, uint32_t n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tuned.find(std::make_tuple(L, K, length_class(n)));
+  return it == g_tuned.end() ? 0 : it->second;
+}
+
 int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
   const int forced = forced_variant();
   if (forced) return forced;
   const uint32_t Lc = L;
-  const uint32_t nc = n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512);
+  const uint32_t nc = length_class(n);
   const auto key = std::make_tuple(Lc, K, nc);
   {
     std::lock_guard<std::mutex> lk(g_mu);

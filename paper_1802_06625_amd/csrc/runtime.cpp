@@ -38,6 +38,7 @@ int g_variant_forced = 0;
 
 namespace prune {
 int forced_variant() { return g_variant_forced; }
+void set_last_error(const char *msg) { g_last_error = msg; }
 // Kernel timing of the direct forward (prune_fb_forward) on this thread.
 bool timing_on() { return g_timing; }
 // A launch is timed only when both of its events exist.

@@ -120,5 +120,7 @@ bool timing_on();
 void timing_restart();
 void timing_push(hipEvent_t e0, hipEvent_t e1);
 int forced_variant();
+// Text returned by prune_last_error on this thread.
+void set_last_error(const char *msg);
 
 }  // namespace prune

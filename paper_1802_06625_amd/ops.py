@@ -76,6 +76,19 @@ def fb_forward(x, taps, frames_dev, Kmax, bank_L, max_frame_len, y=None):
     return y
 
 
+def fb_forward_noalloc(x, taps, frames_dev, Kmax, bank_L, max_frame_len, y):
+    """fb_forward through prune_fb_forward_noalloc: the library allocates
+    nothing (its work list lives in a fixed device array), so y must be
+    given."""
+    S, N = x.shape
+    assert x.is_contiguous() and taps.is_contiguous() and y.is_contiguous()
+    d = make_desc(S, N, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
+    call("prune_fb_forward_noalloc", C.byref(d), C.c_void_p(x.data_ptr()),
+         C.c_void_p(taps.data_ptr()), C.c_void_p(frames_dev.data_ptr()), C.c_void_p(y.data_ptr()),
+         _stream())
+    return y
+
+
 def check_frames(frames_dev, n_streams, stream_len, Kmax, bank_L, max_frame_len):
     """Number of frames the filter-bank operations would skip or that break
     the required order (sorted by stream, then t0, no overlap)."""
