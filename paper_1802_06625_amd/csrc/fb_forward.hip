@@ -44,7 +44,7 @@ __device__ __forceinline__ int pidx(int i) { return i + i / J; }
 // coefficients of a chunk are at constant offsets from one base.  Chunk c
 // holds taps cJ .. cJ+J-1; the last one holds only L - (nchunks-1) J real
 // taps (the rest are zero padding) and stops there.
-template <int KH, int J>
+template <int KH, int J, int G, bool PIPE>
 __device__ __forceinline__ void horner_pass(const float *__restrict__ wre,
                                             const float *__restrict__ wim,
                                             const float *__restrict__ wrr,
@@ -64,54 +64,81 @@ __device__ __forceinline__ void horner_pass(const float *__restrict__ wre,
       xi[w] = wim[q];
       rr[w] = wrr[q];
     }
+    // PIPE: the coefficients of tap i+1 are read from LDS while tap i
+    // computes (every tap index below Lpad is in the table, zero-padded)
+    float2 cn[KH];
+    if (PIPE) {
+#pragma unroll
+      for (int b = 0; b < KH; ++b) cn[b] = cb[b];
+    }
 #pragma unroll
     for (int i = 0; i < J; ++i) {
       if (c * J + i >= L) break;   // uniform: zero-padded taps of the last chunk
       float2 cf[KH];
 #pragma unroll
-      for (int b = 0; b < KH; ++b) cf[b] = cb[i * kMaxKH + b];
+      for (int b = 0; b < KH; ++b) cf[b] = PIPE ? cn[b] : cb[i * kMaxKH + b];
+      if (PIPE && i + 1 < J) {
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const int w = j - i + J - 1;
-        float ar = cf[KH - 1].x, ai = cf[KH - 1].y;
+        for (int b = 0; b < KH; ++b) cn[b] = cb[(i + 1) * kMaxKH + b];
+      }
+      // the Horner chains of G outputs advance together, one branch at a
+      // time, so a wave has 2G independent FMAs in flight
+#pragma unroll
+      for (int j0 = 0; j0 < J; j0 += G) {
+        float ar[G], ai[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          ar[g] = cf[KH - 1].x;
+          ai[g] = cf[KH - 1].y;
+        }
 #pragma unroll
         for (int b = KH - 2; b >= 0; --b) {
-          ar = fmaf(ar, rr[w], cf[b].x);
-          ai = fmaf(ai, rr[w], cf[b].y);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int w = j0 + g - i + J - 1;
+            ar[g] = fmaf(ar[g], rr[w], cf[b].x);
+            ai[g] = fmaf(ai[g], rr[w], cf[b].y);
+          }
         }
-        accr[j] = fmaf(xr[w], ar, accr[j]);
-        accr[j] = fmaf(-xi[w], ai, accr[j]);
-        acci[j] = fmaf(xr[w], ai, acci[j]);
-        acci[j] = fmaf(xi[w], ar, acci[j]);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int j = j0 + g, w = j - i + J - 1;
+          accr[j] = fmaf(xr[w], ar[g], accr[j]);
+          accr[j] = fmaf(-xi[w], ai[g], accr[j]);
+          acci[j] = fmaf(xr[w], ai[g], acci[j]);
+          acci[j] = fmaf(xi[w], ar[g], acci[j]);
+        }
       }
     }
   }
 }
 
-template <int J>
+template <int J, int G, bool PIPE>
 __device__ __forceinline__ void horner_dispatch(int KH, const float *wre, const float *wim,
                                                 const float *wrr, const float2 *coef, int Lpad,
                                                 int L, int t, float *accr, float *acci) {
+#define PRUNE_HP(k) horner_pass<k, J, G, PIPE>(wre, wim, wrr, coef, Lpad, L, t, accr, acci)
   switch (KH) {
     case 0: break;
-    case 1: horner_pass<1, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 2: horner_pass<2, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 3: horner_pass<3, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 4: horner_pass<4, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 5: horner_pass<5, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 6: horner_pass<6, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 7: horner_pass<7, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 8: horner_pass<8, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    case 9: horner_pass<9, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
-    default: horner_pass<10, J>(wre, wim, wrr, coef, Lpad, L, t, accr, acci); break;
+    case 1: PRUNE_HP(1); break;
+    case 2: PRUNE_HP(2); break;
+    case 3: PRUNE_HP(3); break;
+    case 4: PRUNE_HP(4); break;
+    case 5: PRUNE_HP(5); break;
+    case 6: PRUNE_HP(6); break;
+    case 7: PRUNE_HP(7); break;
+    case 8: PRUNE_HP(8); break;
+    case 9: PRUNE_HP(9); break;
+    default: PRUNE_HP(10); break;
   }
+#undef PRUNE_HP
 }
 
 // Persistent forward kernel: each workgroup takes tile blockIdx.x, then
 // further tiles from the item list with an atomic ticket (offset by the grid
 // size) until the list is exhausted.  *ticket must be zero at launch (the
 // producer of the item list clears it).
-template <int J, int WG, int WAVES>
+template <int J, int WG, int WAVES, int G, bool PIPE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void k_fb_forward(const FbFrameDesc *__restrict__ frames,
                                                    const WorkItem *__restrict__ items,
@@ -246,8 +273,8 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
         // a wave whose outputs all lie beyond the frame's end (the last tile
         // of a frame) stores nothing and skips the arithmetic (KH 0); the
         // condition is uniform across the wave
-        horner_dispatch<J>(n0 + (t & ~63) * J < n ? KH : 0, wre, wim, wrr, coef, Lpad, L, t, accr,
-                           acci);
+        horner_dispatch<J, G, PIPE>(n0 + (t & ~63) * J < n ? KH : 0, wre, wim, wrr, coef, Lpad, L,
+                                    t, accr, acci);
       }
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -278,27 +305,32 @@ struct FbVariant {
 
 // With events, the dispatch itself records the kernel's start and end
 // (hipExtLaunchKernelGGL): no marker packets, no gaps around the kernel.
-template <int J, int WG, int WAVES>
+template <int J, int WG, int WAVES, int G = J, bool PIPE = false>
 static void launch_fwd(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
                        unsigned int *ticket, uint32_t grid, hipStream_t s, hipEvent_t e0,
                        hipEvent_t e1) {
   if (e0 || e1)
-    hipExtLaunchKernelGGL((k_fb_forward<J, WG, WAVES>), dim3(grid), dim3(WG), 0, s, e0, e1, 0, f, it, n,
-                          ticket);
+    hipExtLaunchKernelGGL((k_fb_forward<J, WG, WAVES, G, PIPE>), dim3(grid), dim3(WG), 0, s, e0, e1, 0,
+                          f, it, n, ticket);
   else
-    hipLaunchKernelGGL((k_fb_forward<J, WG, WAVES>), dim3(grid), dim3(WG), 0, s, f, it, n, ticket);
+    hipLaunchKernelGGL((k_fb_forward<J, WG, WAVES, G, PIPE>), dim3(grid), dim3(WG), 0, s, f, it, n,
+                       ticket);
 }
 
 static const FbVariant kVariants[] = {
-    {"valu_horner_J8_WG256_w2", 8 * 256, 256, launch_fwd<8, 256, 2>},
+    // vector Horner kernels: J outputs per lane, WG threads, waves-per-EU
+    // hint, Horner chains of G outputs advanced together, next tap's
+    // coefficients read ahead (p) or not (g)
+    {"valu_horner_J8_WG256_p4", 8 * 256, 256, launch_fwd<8, 256, 1, 4, true>},
     {"valu_horner_J4_WG256_w3", 4 * 256, 256, launch_fwd<4, 256, 3>},
     {"valu_horner_J8_WG128_w2", 8 * 128, 128, launch_fwd<8, 128, 2>},
     {"valu_horner_J4_WG128_w4", 4 * 128, 128, launch_fwd<4, 128, 4>},
-    {"valu_horner_J8_WG256_w1", 8 * 256, 256, launch_fwd<8, 256, 1>},
+    {"valu_horner_J8_WG256_g8", 8 * 256, 256, launch_fwd<8, 256, 1, 8, false>},
     // matrix-core block-Toeplitz kernels: NT result tiles per wave, NW waves
     {"mfma_toeplitz_NT4_W4", 4 * 256 * 4, 256, launch_fb_mfma<4, 4>},
     {"mfma_toeplitz_NT2_W4", 2 * 256 * 4, 256, launch_fb_mfma<2, 4>},
     {"mfma_toeplitz_NT4_W2", 4 * 256 * 2, 128, launch_fb_mfma<4, 2>},
+    {"valu_horner_J8_WG256_p2", 8 * 256, 256, launch_fwd<8, 256, 1, 2, true>},
 };
 
 int fb_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
