@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-per-frame", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--only-c2", action="store_true", help="skip the other workloads")
-    p.add_argument("--only", default="", help="run one secondary workload only: c3, c4, c4fit, c5, c5bwd, c2u, paper, host, motion")
+    p.add_argument("--only", default="", help="run one secondary workload only: c1, c3, c4, c4fit, c5, c5bwd, c2u, paper, host, motion, perframe")
     p.add_argument("--ceilings", action="store_true",
                    help="only the ceiling probes (copy bandwidth, unpacked fp32 FMA, fp32 MFMA)")
     p.add_argument("--copy-calib", action="store_true",
@@ -177,7 +177,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.only:
-        fn = {"c3": lambda: bench_c3(args.steps, args.warmup),
+        fn = {"c1": lambda: bench_c1(args.steps, args.warmup),
+              "perframe": lambda: bench_per_frame("C2"),
+              "c3": lambda: bench_c3(args.steps, args.warmup),
               "c4": lambda: bench_direct("C4", args.steps, args.warmup),
               "c4fit": lambda: bench_fit(),
               "c5": lambda: bench_c5(args.steps, args.warmup),
@@ -227,37 +229,30 @@ def main():
     g.fire(L.BATCHED_GRAPH, F)
     g.sync()
     first = pg.fifo_out.view(F, n)[: min(F, 1024)].cpu().numpy() if not args.profile_only else None
-    for _ in range(args.warmup):
-        g.fire(L.BATCHED_GRAPH, F)
-    torch.cuda.synchronize()
     print("bench: timing", file=sys.stderr, flush=True)
-    st = torch.cuda.current_stream()
-
-    def timed(mode):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record(st)
-        for _ in range(args.steps):
-            g.fire(mode, F)
-        e1.record(st)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        g.sync()
-        return wall * 1e3 / args.steps, e0.elapsed_time(e1) / args.steps
 
     # The batch as one hipGraph replay, and as the same launch sequence on the
-    # stream; the step is reported in the faster mode and both are listed.
-    # During the stream-mode steps the library records HIP events around every
-    # forward-kernel launch on the launch stream (the kernel's duration for
-    # the roofline; graph replays cannot be timed from inside).
-    graph_ms, graph_ev = timed(L.BATCHED_GRAPH)
-    for _ in range(args.warmup):
-        g.fire(L.BATCHED, F)
-    ops.timing_enable(True)
-    stream_ms, stream_ev = timed(L.BATCHED)
-    k_total_ms, k_launches = ops.last_fb_kernel_ms()
-    ops.timing_enable(False)
+    # stream, timed in alternating blocks; the step is reported in the faster
+    # mode and both are listed.  During the stream-mode blocks the library
+    # records HIP events around every forward-kernel launch on the launch
+    # stream (the kernel's duration for the roofline; graph replays cannot be
+    # timed from inside).
+    ktime = [0.0, 0]
+
+    def on_stream(on):
+        if on:
+            ops.timing_enable(True)
+        else:
+            ms_, n_ = ops.last_fb_kernel_ms()
+            ktime[0] += ms_
+            ktime[1] += n_
+            ops.timing_enable(False)
+
+    graph_ev, stream_ev, graph_ms, stream_ms = _time_modes(
+        lambda: g.fire(L.BATCHED_GRAPH, F), lambda: g.fire(L.BATCHED, F), args.steps, args.warmup,
+        on_stream, with_wall=True)
+    g.sync()
+    k_total_ms, k_launches = ktime
     if graph_ms <= stream_ms:
         mode_name, ms_step, ev_ms_step = "batched_graph", graph_ms, graph_ev
     else:
@@ -287,6 +282,17 @@ def main():
     achieved = flops / (k_ms * 1e-3) / 1e12
     traffic = measured_traffic(os.path.join(ROOT, "paper_1802_06625_amd", "csrc", "fb_forward.hip"),
                                os.path.join(ROOT, "profiles", "fb_forward_c2_traffic.txt"))
+    # what the Horner kernel executes: 2(KH-1)+4 fp32 FMAs per output and tap
+    # (KH = highest active branch, K under prefix masks), beside the measured
+    # ceiling of all-register fp32 FMAs (two-operand accumulate form, 8 waves
+    # per SIMD) on this device
+    from paper_1802_06625_amd import _lib as Lb
+    import ctypes as C
+    fma_lanes = float(np.sum(side[:, 1].astype(np.float64) * Lt * (2.0 * side[:, 0] + 2.0)))
+    pr = Lb.ProbeResult()
+    Lb.call("prune_probe_ceiling", Lb.PROBE_FMAC32, 8, 4096, 5, C.byref(pr))
+    ceil_tf = 2.0 * pr.rate / 1e12
+    exec_tf = 2.0 * fma_lanes / (k_ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": round(achieved, 2),
                        "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
@@ -294,22 +300,24 @@ def main():
                        "kernel": "k_fb_forward", "kernel_ms": round(k_ms, 4),
                        "kernel_launches_timed": k_launches,
                        "algorithmic_flops_per_launch": flops,
-                       "hbm_gbps_algorithmic": round(16.0 * samples / (k_ms * 1e-3) / 1e9, 1)}
-
-    if not args.no_per_frame:
-        print("bench: per-frame firing", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.fire(L.PER_FIRING, 4 * F)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out["per_frame_msamples"] = round(samples / el / 1e6, 1)
-        out["batched_vs_per_frame"] = round(value / out["per_frame_msamples"], 1)
+                       "hbm_gbps_algorithmic": round(16.0 * samples / (k_ms * 1e-3) / 1e9, 1),
+                       "executed": {"fma_lanes_per_launch": fma_lanes, "tflops": round(exec_tf, 2),
+                                    "measured_fp32_fma_ceiling_tflops": round(ceil_tf, 2),
+                                    "ceiling_clock_ghz": round(pr.clock_ghz, 3),
+                                    "frac_of_measured_ceiling": round(exec_tf / ceil_tf, 4)}}
 
     del g, pg
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if not args.no_per_frame:
+        print("bench: per-frame firing", file=sys.stderr, flush=True)
+        pf = bench_per_frame("C2")
+        out["per_frame"] = pf
+        out["per_frame_msamples"] = pf["msamples_mean"]
+        out["batched_vs_per_frame"] = round(value / pf["msamples_mean"], 1)
     if not args.only_c2:
+        print("bench: plain graph, 64 frames", file=sys.stderr, flush=True)
+        out["c1"] = bench_c1(args.steps, args.warmup)
         print("bench: unfused DPD graph", file=sys.stderr, flush=True)
         out["c2_unfused"] = bench_c2_unfused(min(args.steps, 10), min(args.warmup, 5), ms_step)
         print("bench: motion detection", file=sys.stderr, flush=True)
@@ -331,7 +339,87 @@ def main():
         print("bench: oracle baseline", file=sys.stderr, flush=True)
         wl2 = synth.make("C2", n_frames=args.frames or None)
         out["cpu_baseline"] = cpu_baseline(wl2, args.cpu_seconds, first)
+        if not args.only_c2:
+            out["oracle_timings"] = oracle_timings()
     print(json.dumps(out))
+
+
+def bench_per_frame(name, C=3, warm=3, runs=8, frames=None):
+    """The paper's execution model as the baseline: one decode and one
+    filter-bank launch per firing, in host order, through FIFOs of C = 3
+    blocks (the paper's triple buffering), frames resident in HBM.  A run
+    fires the whole batch; 3 warm-up runs, then 8 timed runs (host clock
+    around each, device synchronised on both sides), mean and median."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import PlainGraph
+    wl = synth.make(name, n_frames=frames)
+    side = wl.side[0]
+    n = side[:, 1].astype(np.int64)
+    F = len(n)
+    param = bool(np.any(n != n[0]))
+    atr = int(wl.spec.n_max) if param else int(n[0])
+    pg = PlainGraph(wl.Kmax, wl.bank_L, atr, C, param)
+    g = pg.g
+    g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    x = torch.from_numpy(wl.x[0]).cuda()
+    samples = int(n.sum())
+    times = []
+    for r in range(warm + runs):
+        g.source_push(pg.src, x, n)
+        g.config_push(pg.cfg, side)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.fire(L.PER_FIRING)
+        torch.cuda.synchronize()
+        if r >= warm:
+            times.append(time.perf_counter() - t0)
+        g.sync()
+    rates = [samples / t / 1e6 for t in times]
+    res = {"workload": f"{wl.spec.description}; per-frame firing, C={C}", "frames": F,
+           "samples": samples, "runs": runs, "warmup_runs": warm,
+           "msamples_mean": round(float(np.mean(rates)), 2),
+           "msamples_median": round(float(np.median(rates)), 2),
+           "seconds_per_run_mean": round(float(np.mean(times)), 4)}
+    del g, pg, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_c1(steps, warmup):
+    """The small plain graph (64 frames x 1024, K~U{1..4}, L=8): absolute
+    numbers, batched (both launch modes) and per-frame with C = 3."""
+    import torch
+    import synth
+    from paper_1802_06625_amd import _lib as L
+    from paper_1802_06625_amd.graph import PlainGraph
+    wl = synth.make("C1")
+    side = wl.side[0]
+    F, n = side.shape[0], int(side[0, 1])
+    pg = PlainGraph(wl.Kmax, wl.bank_L, n, F)
+    g = pg.g
+    g.set_taps(pg.fb, torch.from_numpy(wl.taps[0]).cuda())
+    pg.fifo_in.view(F, n).copy_(torch.from_numpy(wl.x[0]).view(F, n))
+    for _ in range(2 * (steps + warmup) + 1):
+        g.source_push(pg.src, None, side[:, 1])
+        g.config_push(pg.cfg, side)
+    torch.cuda.synchronize()
+    g.fire(L.BATCHED_GRAPH, F)
+    ms_graph, ms_stream = _time_modes(lambda: g.fire(L.BATCHED_GRAPH, F), lambda: g.fire(L.BATCHED, F),
+                                      steps, warmup)
+    g.sync()
+    ms = min(ms_graph, ms_stream)
+    samples = F * n
+    res = {"workload": wl.spec.description, "samples": samples,
+           "msamples": round(samples / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
+           "mode": "batched_graph" if ms_graph <= ms_stream else "batched_stream",
+           "graph_ms": round(ms_graph, 4), "stream_ms": round(ms_stream, 4)}
+    del g, pg
+    torch.cuda.empty_cache()
+    res["per_frame"] = bench_per_frame("C1")
+    res["batched_vs_per_frame"] = round(res["msamples"] / res["per_frame"]["msamples_mean"], 1)
+    return res
 
 
 def _time_events(fn, steps, warmup):
@@ -347,6 +435,45 @@ def _time_events(fn, steps, warmup):
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def _time_modes(fire_graph, fire_stream, steps, warmup, on_stream=None, with_wall=False):
+    """Milliseconds per step of the two batched launch modes: both warmed up
+    first, then timed in alternating blocks (graph, stream, graph, stream),
+    so that neither mode lands in the other's warm-up.  on_stream(True/False)
+    brackets every stream-mode block (kernel timing).  with_wall: also the
+    host wall-clock milliseconds per step of each mode, each block bracketed
+    by device synchronisations."""
+    import torch
+    for _ in range(warmup):
+        fire_graph()
+        fire_stream()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    nb = 2 if steps >= 2 else 1
+    sizes = [steps // nb + (1 if b < steps % nb else 0) for b in range(nb)]
+    tot = {"graph": 0.0, "stream": 0.0}
+    wall = {"graph": 0.0, "stream": 0.0}
+    for k in sizes:
+        for name, fn in (("graph", fire_graph), ("stream", fire_stream)):
+            if name == "stream" and on_stream:
+                on_stream(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(st)
+            for _ in range(k):
+                fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            wall[name] += time.perf_counter() - t0
+            tot[name] += e0.elapsed_time(e1)
+            if name == "stream" and on_stream:
+                on_stream(False)
+    if with_wall:
+        return (tot["graph"] / steps, tot["stream"] / steps,
+                wall["graph"] * 1e3 / steps, wall["stream"] * 1e3 / steps)
+    return tot["graph"] / steps, tot["stream"] / steps
 
 
 def bench_fit(steps=200, lr=1e-2):
@@ -457,13 +584,19 @@ def bench_direct(name, steps, warmup):
            "bwd_tflops_alg": round(f_bwd / (t_b * 1e-3) / 1e12, 2),
            "fwd_bwd_frac_of_fp32_vector_peak": round((f_fwd + f_bwd) / ((t_f + t_b) * 1e-3) / 1e12
                                                       / PEAK_FP32_VECTOR_TFLOPS, 4),
-           "fwd_variant": ops.variant_names()[ops.autotuned_variant(L, wl.Kmax, mfl) - 1],
+           "fwd_variant": ops.variant_names()[ops.tuned_variant(x, fr, wl.Kmax, wl.bank_L, mfl) - 1],
            "bwd_form": ops.bwd_variant_name(ops.autotuned_bwd_variant(L, wl.Kmax, mfl)),
            "bwd_ms_by_form": bwd_by_form}
     if by_variant:
         res["fwd_ms_by_variant"] = by_variant
         res["fwd_tflops_alg_by_variant"] = {k: round(f_fwd / (v * 1e-3) / 1e12, 2)
                                             for k, v in by_variant.items()}
+    # accuracy of what was timed: one more forward and adjoint in the timed
+    # configuration, against the oracle on the compared streams
+    fwd()
+    bwd()
+    torch.cuda.synchronize()
+    res["accuracy"] = direct_accuracy(wl, y, gx, gt, streams=range(min(S, 4)))
     if name == "C5":
         # matrix-core kernel (block-Toeplitz form): the fastest of its
         # variants, kernel duration from the library's HIP events on the
@@ -491,6 +624,81 @@ def bench_direct(name, steps, warmup):
                                 "kernel_ms": round(k_ms, 4), "algorithmic_flops_per_launch": f_fwd}
     del x, taps, gy, y, gx, gt, work
     torch.cuda.empty_cache()
+    return res
+
+
+def direct_accuracy(wl, y, gx, gt, streams):
+    """Relative L2 error (Re and Im as reals) of the device forward output,
+    input gradient and tap gradient against the FP64 oracle's closed forms,
+    over the given streams (each in full)."""
+    from oracle.filterbank import fb_stream, fb_stream_adjoint
+    from oracle.graphs import stream_frames
+    yd, gxd, gtd = y.cpu().numpy(), gx.cpu().numpy(), gt.cpu().numpy()
+    err = {"y": [0.0, 0.0], "grad_x": [0.0, 0.0], "grad_taps": [0.0, 0.0]}
+    streams = list(streams)
+    for s_ in streams:
+        fr = stream_frames(wl, s_)
+        ry = fb_stream(wl.x[s_], fr, wl.taps[s_], wl.bank_L, wl.Kmax)
+        rx, rt = fb_stream_adjoint(wl.x[s_], fr, wl.taps[s_], wl.bank_L, wl.Kmax, wl.gy[s_])
+        for k, a, b in (("y", yd[s_], ry), ("grad_x", gxd[s_], rx), ("grad_taps", gtd[s_], rt)):
+            d = np.asarray(a, np.complex128) - b
+            err[k][0] += float(np.vdot(d, d).real)
+            err[k][1] += float(np.vdot(b, b).real)
+    out = {k: float(np.sqrt(v[0] / v[1])) for k, v in err.items()}
+    out["streams_compared"] = len(streams)
+    out["samples_compared"] = int(len(streams) * wl.x.shape[1])
+    return out
+
+
+def oracle_timings():
+    """The oracle as it stands (numpy FP64, single thread) on the other
+    workloads: the 64-frame plain graph and the differentiation workload in
+    full, the uneven-frame and wide multi-stream workloads on their first 64
+    frames.  Msamples/s of input."""
+    import synth
+    from oracle import graphs as og
+    from oracle.filterbank import fb_stream, fb_stream_adjoint
+    from oracle.graphs import stream_frames
+    cores = len(os.sched_getaffinity(0))
+    res = {"cores": 1, "cores_visible": cores, "kind": "oracle", "precision": "float64"}
+    wl = synth.make("C1")
+    t0 = time.perf_counter()
+    og.run_plain(wl, C=3)
+    el = time.perf_counter() - t0
+    res["c1_graph_full"] = {"samples": int(wl.x.size), "seconds": round(el, 4),
+                            "msamples": round(wl.x.size / el / 1e6, 3)}
+    wl = synth.make("C4", cotangent=True)
+    fr = stream_frames(wl, 0)
+    t0 = time.perf_counter()
+    fb_stream(wl.x[0], fr, wl.taps[0], wl.bank_L, wl.Kmax)
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fb_stream_adjoint(wl.x[0], fr, wl.taps[0], wl.bank_L, wl.Kmax, wl.gy[0])
+    tb = time.perf_counter() - t0
+    res["c4_full"] = {"samples": int(wl.x.size), "fwd_seconds": round(tf, 3), "bwd_seconds": round(tb, 3),
+                      "fwd_msamples": round(wl.x.size / tf / 1e6, 3),
+                      "fwd_bwd_msamples": round(wl.x.size / (tf + tb) / 1e6, 3)}
+    wl = synth.make("C3")
+    n64 = int(wl.side[0, :64, 1].sum())
+    sub = synth.Workload(wl.spec, wl.side[:, :64].copy(), wl.x[:, :n64].copy(), wl.taps)
+    t0 = time.perf_counter()
+    og.run_plain(sub, C=3)
+    el = time.perf_counter() - t0
+    res["c3_first_64_frames"] = {"samples": n64, "seconds": round(el, 3), "msamples": round(n64 / el / 1e6, 3)}
+    wl = synth.make("C5", cotangent=True)
+    S64 = 64 // wl.n_frames
+    t0 = time.perf_counter()
+    for s_ in range(S64):
+        fb_stream(wl.x[s_], stream_frames(wl, s_), wl.taps[s_], wl.bank_L, wl.Kmax)
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for s_ in range(S64):
+        fb_stream_adjoint(wl.x[s_], stream_frames(wl, s_), wl.taps[s_], wl.bank_L, wl.Kmax, wl.gy[s_])
+    tb = time.perf_counter() - t0
+    n = S64 * wl.x.shape[1]
+    res["c5_first_64_frames"] = {"samples": n, "streams": S64, "fwd_seconds": round(tf, 3),
+                                 "bwd_seconds": round(tb, 3), "fwd_msamples": round(n / tf / 1e6, 3),
+                                 "fwd_bwd_msamples": round(n / (tf + tb) / 1e6, 3)}
     return res
 
 
@@ -525,8 +733,8 @@ def bench_c2_unfused(steps, warmup, fused_ms):
         g.config_push(ug.cfg, side)
     torch.cuda.synchronize()
     g.fire(L.BATCHED_GRAPH, F)
-    ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
-    ms_stream = _time_events(lambda: g.fire(L.BATCHED, F), steps, warmup)
+    ms_graph, ms_stream = _time_modes(lambda: g.fire(L.BATCHED_GRAPH, F), lambda: g.fire(L.BATCHED, F),
+                                      steps, warmup)
     g.sync()
     ms = min(ms_graph, ms_stream)
     samples = F * n
@@ -578,8 +786,8 @@ def bench_paper_dpd(steps, warmup):
             g.config_push(G.cfg, side)
         torch.cuda.synchronize()
         g.fire(L.BATCHED_GRAPH, F)
-        ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
-        ms_stream = _time_events(lambda: g.fire(L.BATCHED, F), steps, warmup)
+        ms_graph, ms_stream = _time_modes(lambda: g.fire(L.BATCHED_GRAPH, F),
+                                          lambda: g.fire(L.BATCHED, F), steps, warmup)
         g.sync()
         ms = min(ms_graph, ms_stream)
         res[name] = {"msamples": round(F * n / (ms * 1e-3) / 1e6, 1), "ms_per_batch": round(ms, 4),
@@ -649,8 +857,8 @@ def bench_motion(steps, warmup, batch=64):
         g.source_push(mg.src, None, np.full(batch, npix))
     torch.cuda.synchronize()
     g.fire(L.BATCHED_GRAPH, batch)
-    ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, batch), steps, warmup)
-    ms_stream = _time_events(lambda: g.fire(L.BATCHED, batch), steps, warmup)
+    ms_graph, ms_stream = _time_modes(lambda: g.fire(L.BATCHED_GRAPH, batch),
+                                      lambda: g.fire(L.BATCHED, batch), steps, warmup)
     g.sync()
     ms = min(ms_graph, ms_stream)
     fps = batch / (ms * 1e-3)
@@ -694,11 +902,23 @@ def bench_c3(steps, warmup):
         g.config_push(pg.cfg, side)
     torch.cuda.synchronize()
     g.fire(L.BATCHED_GRAPH, F)
-    ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
-    ms_stream = _time_events(lambda: g.fire(L.BATCHED, F), steps, warmup)
+    ms_graph, ms_stream = _time_modes(lambda: g.fire(L.BATCHED_GRAPH, F), lambda: g.fire(L.BATCHED, F),
+                                      steps, warmup)
     g.sync()
     ms = min(ms_graph, ms_stream)
     samples = int(n.sum())
+    # accuracy of the last timed batch on its first 64 frames: the oracle on
+    # those frames with the previous batch's last samples as the history
+    from oracle.filterbank import fb_stream
+    from oracle.graphs import stream_frames
+    H = max(wl.bank_L) - 1
+    fr64 = stream_frames(wl, 0)[:64]
+    n64 = int(sum(f[1] for f in fr64))
+    xc = np.concatenate([wl.x[0, samples - H:samples], wl.x[0, :n64]])
+    ref = fb_stream(xc, [(0, H, 0, 0)] + [(t0 + H, m, k, r) for (t0, m, k, r) in fr64], wl.taps[0],
+                    wl.bank_L, wl.Kmax)[H:]
+    dev = np.concatenate([pg.fifo_out.view(F, atr)[f, :n[f]].cpu().numpy() for f in range(64)])
+    rel64 = float(np.linalg.norm(dev.astype(np.complex128) - ref) / np.linalg.norm(ref))
     Lb = np.array(wl.bank_L, dtype=np.float64)[side[:, 2]]
     flops = float(np.sum(n * (4.0 + side[:, 0] * (8.0 * Lb + 3.0))))
     res = {"workload": wl.spec.description, "samples": samples, "frames": F,
@@ -706,7 +926,8 @@ def bench_c3(steps, warmup):
            "mode": "batched_graph" if ms_graph <= ms_stream else "batched_stream",
            "graph_ms": round(ms_graph, 4), "stream_ms": round(ms_stream, 4),
            "tflops_alg": round(flops / (ms * 1e-3) / 1e12, 2),
-           "frac_of_fp32_vector_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)}
+           "frac_of_fp32_vector_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+           "rel_l2_first_64_frames_of_last_batch": rel64}
     del g, pg
     torch.cuda.empty_cache()
     return res
@@ -734,8 +955,8 @@ def bench_c5(steps, warmup):
             g.config_push(ids["cfg"], wl.side[s])
     torch.cuda.synchronize()
     g.fire(L.BATCHED_GRAPH, F)
-    ms_graph = _time_events(lambda: g.fire(L.BATCHED_GRAPH, F), steps, warmup)
-    ms_stream = _time_events(lambda: g.fire(L.BATCHED, F), steps, warmup)
+    ms_graph, ms_stream = _time_modes(lambda: g.fire(L.BATCHED_GRAPH, F), lambda: g.fire(L.BATCHED, F),
+                                      steps, warmup)
     g.sync()
     ms = min(ms_graph, ms_stream)
     samples = S * F * n

@@ -575,10 +575,33 @@ const char *prune_fb_variant_name(int variant);
 int prune_fb_variant_count(void);
 
 /* Run the autotuner now for the given shape class (taps L, branches K,
- * frame length n) and report the chosen variant.  Uses the device's null
- * stream; results are cached per process and in the file named by the
- * PRUNE_AUTOTUNE_CACHE environment variable when set. */
+ * frame length n) on a synthetic batch with a graph's structure (one bank,
+ * every frame n samples, prefix masks of a uniform branch count) and report
+ * the chosen variant: the one a graph with this filter bank uses.  Uses the
+ * device's null stream.
+ *
+ * Autotuning in general: prune_fb_forward and prune_fb_backward tune on the
+ * first call of a shape class (banks and tap counts, Kmax, frame-length
+ * class; for the adjoint also whether grad_x is wanted) by timing every
+ * variant on that call's own inputs, five alternating rounds of single
+ * launches each timed by events, smallest median wins.  Graphs tune at
+ * finalize on a synthetic batch of their own structure (banks, rate,
+ * variable-rate ports drawing log-uniform frame lengths).  Choices are kept
+ * per process and, when the environment variable PRUNE_AUTOTUNE_CACHE names
+ * a file, appended to it as JSON lines {"key", "choice", "ms"} and read
+ * back by later processes (keys include the device architecture), which
+ * then run no tuning launches.  PRUNE_AUTOTUNE=0 disables tuning (variant 1
+ * unless the cache file has a choice). */
 prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant);
+
+/* Autotuning in this process so far: tuning runs (forward or backward,
+ * each one shape class) and choices taken from the PRUNE_AUTOTUNE_CACHE
+ * file instead of tuning. */
+prune_status prune_autotune_counts(uint32_t *tuning_runs, uint32_t *cache_hits);
+
+/* The forward variant prune_fb_forward uses for desc's shape class: the
+ * forced one, else the one tuned in this process, else 0 (not tuned yet). */
+prune_status prune_fb_tuned_variant(const prune_fb_desc *desc, int *variant);
 
 /* Backward form: 0 = automatic (autotuned per shape class like the forward,
  * cached per process), 1 = vector kernel (Horner form in r), 2 = matrix-core
@@ -587,7 +610,9 @@ prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant)
  * the same deterministic float64 reduction of grad_h. */
 prune_status prune_set_bwd_variant(int variant);
 const char *prune_bwd_variant_name(int variant);
-/* Run the backward autotuner now for (L, K, n) and report the chosen form. */
+/* Run the backward autotuner now for (L, K, n) on a synthetic batch
+ * (uniform frames of n samples, every branch, grad_x wanted) and report
+ * the chosen form. */
 prune_status prune_autotune_bwd(uint32_t L, uint32_t K, uint32_t n, int *variant);
 
 /* Device-side timing of the filter-bank forward kernel launches made on this

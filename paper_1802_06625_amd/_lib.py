@@ -129,6 +129,8 @@ SIGNATURES = [
     ("prune_fb_variant_name", C.c_char_p, [C.c_int]),
     ("prune_fb_variant_count", C.c_int, []),
     ("prune_autotune_fb", _ST, [C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int)]),
+    ("prune_autotune_counts", _ST, [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]),
+    ("prune_fb_tuned_variant", _ST, [C.POINTER(FbDesc), C.POINTER(C.c_int)]),
     ("prune_fb_check_frames", _ST, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p]),
     ("prune_set_bwd_variant", _ST, [C.c_int]),
     ("prune_bwd_variant_name", C.c_char_p, [C.c_int]),

@@ -4,7 +4,9 @@
 // same persistent forward kernel as the graph executor.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -139,7 +141,16 @@ struct DirectScratch {
   size_t cap_frames = 0, cap_items = 0;
 };
 std::map<int, DirectScratch> g_scratch;
-std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int> g_tuned;
+std::map<std::string, int> g_tuned;   // graph-path shape classes -> variant
+// The direct forward's choices by (Lmax, Kmax, frame-length class), in a
+// fixed table so that the allocation-free entry point can read them.
+struct DirectChoice {
+  uint32_t L, K, nc;
+  int v;
+};
+constexpr int kMaxChoices = 64;
+DirectChoice g_choice[kMaxChoices];
+int g_n_choice = 0;
 int g_ncu = 0;
 
 prune_status check_desc(const prune_fb_desc *d) {
@@ -201,8 +212,9 @@ unsigned char *noalloc_workspace() {
 }  // namespace
 
 namespace prune {
-int choose_variant(uint32_t L, uint32_t K, uint32_t n);
 int cached_variant(uint32_t L, uint32_t K, uint32_t n);
+static int choose_direct_variant(const prune_fb_desc *desc, const void *x, const void *taps,
+                                 const void *frames, void *y, prune_stream_t stream);
 
 prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, const void *taps,
                                       const void *frames, void *y, int variant,
@@ -261,9 +273,9 @@ prune_status prune_fb_forward(const prune_fb_desc *desc, const void *x, const vo
                               const void *frames, void *y, prune_stream_t stream) {
   prune_status st = check_desc(desc);
   if (st != PRUNE_OK) return st;
-  uint32_t Lmax = 1;
-  for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
-  const int v = choose_variant(Lmax, desc->Kmax, desc->max_frame_len);
+  if (!x || !taps || !frames || !y) return PRUNE_E_ARG;
+  if (desc->n_frames == 0) return PRUNE_OK;
+  const int v = choose_direct_variant(desc, x, taps, frames, y, stream);
   return prune_fb_forward_variant(desc, x, taps, frames, y, v, stream);
 }
 
@@ -324,9 +336,20 @@ prune_status prune_fb_check_frames(const prune_fb_desc *desc, const void *frames
   return st;
 }
 
+prune_status prune_fb_tuned_variant(const prune_fb_desc *desc, int *variant) {
+  prune_status st = check_desc(desc);
+  if (st != PRUNE_OK) return st;
+  if (!variant) return PRUNE_E_ARG;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
+  const int f = forced_variant();
+  *variant = f ? f : cached_variant(Lmax, desc->Kmax, desc->max_frame_len);
+  return PRUNE_OK;
+}
+
 prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant) {
   if (L < 1 || L > PRUNE_MAX_L || K < 1 || K > 10 || n < 1) return PRUNE_E_ARG;
-  const int v = choose_variant(L, K, n);
+  const int v = choose_variant_graph(1, &L, K, n, false);
   if (variant) *variant = v;
   return PRUNE_OK;
 }
@@ -335,102 +358,182 @@ prune_status prune_autotune_fb(uint32_t L, uint32_t K, uint32_t n, int *variant)
 
 namespace prune {
 
-extern int forced_variant();
-
-// Time each forward variant on a synthetic batch of the shape class and keep
-// the fastest.  Key: (L, K, frame length class); L is exact because the
-// kernels pad the tap count to different chunk sizes.
 static uint32_t length_class(uint32_t n) { return n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512); }
 
-// The variant the autotuner already chose in this process for the shape
-// class, or 0; never tunes.
-int cached_variant(uint32_t L, uint32_t K, uint32_t n) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_tuned.find(std::make_tuple(L, K, length_class(n)));
-  return it == g_tuned.end() ? 0 : it->second;
+static std::string bank_list(uint32_t n_banks, const uint32_t *L) {
+  std::string r;
+  for (uint32_t b = 0; b < n_banks; ++b) r += (b ? "," : "") + std::to_string(L[b]);
+  return r;
 }
 
-int choose_variant(uint32_t L, uint32_t K, uint32_t n) {
+// The variant the autotuner already chose in this process for the direct
+// forward's shape class, or 0; never tunes and never allocates.
+int cached_variant(uint32_t L, uint32_t K, uint32_t n) {
+  const uint32_t nc = length_class(n);
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < g_n_choice; ++i)
+    if (g_choice[i].L == L && g_choice[i].K == K && g_choice[i].nc == nc) return g_choice[i].v;
+  return 0;
+}
+
+static int variant_index(const std::string &name) {
+  for (int v = 1; v <= fb_variant_count(); ++v)
+    if (name == fb_variant_name(v)) return v;
+  return 0;
+}
+
+// Time every forward variant on one batch: a warm-up launch of each, then
+// kRounds rounds that launch every variant once in turn, each launch timed
+// by its own events on `stream`; the smallest median wins.  Returns 0 when
+// events cannot be created.
+static int time_variants(const prune_fb_desc *d, const void *x, const void *taps, const void *frames,
+                         void *y, prune_stream_t stream, float *best_ms) {
+  constexpr int kRounds = 5;
+  const int nv = fb_variant_count();
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<hipEvent_t> ev(2 * kRounds * nv, nullptr);
+  bool ok = true;
+  for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+  int best = 0;
+  if (ok) {
+    g_tuning = true;
+    for (int v = 1; v <= nv; ++v) prune_fb_forward_variant(d, x, taps, frames, y, v, stream);
+    for (int r = 0; r < kRounds; ++r)
+      for (int v = 1; v <= nv; ++v) {
+        hipEvent_t *e = &ev[2 * (r * nv + v - 1)];
+        (void)hipEventRecord(e[0], s);
+        prune_fb_forward_variant(d, x, taps, frames, y, v, stream);
+        (void)hipEventRecord(e[1], s);
+      }
+    g_tuning = false;
+    if (hipStreamSynchronize(s) == hipSuccess) {
+      float bm = 1e30f;
+      for (int v = 1; v <= nv; ++v) {
+        std::vector<float> t(kRounds);
+        for (int r = 0; r < kRounds; ++r) {
+          hipEvent_t *e = &ev[2 * (r * nv + v - 1)];
+          if (hipEventElapsedTime(&t[r], e[0], e[1]) != hipSuccess) t[r] = 1e30f;
+        }
+        std::sort(t.begin(), t.end());
+        if (t[kRounds / 2] < bm) {
+          bm = t[kRounds / 2];
+          best = v;
+        }
+      }
+      *best_ms = bm;
+    }
+  }
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return best;
+}
+
+// The direct forward tunes on the call's own frames, input and taps (the
+// output is rewritten by the call that follows), once per shape class
+// (Lmax, Kmax, frame-length class) and process, unless the cache file
+// already holds a choice for the class on this architecture.
+static int choose_direct_variant(const prune_fb_desc *desc, const void *x, const void *taps,
+                                 const void *frames, void *y, prune_stream_t stream) {
   const int forced = forced_variant();
   if (forced) return forced;
-  const uint32_t Lc = L;
-  const uint32_t nc = length_class(n);
-  const auto key = std::make_tuple(Lc, K, nc);
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
+  const uint32_t K = desc->Kmax, nc = length_class(desc->max_frame_len);
+  if (int v = cached_variant(Lmax, K, desc->max_frame_len)) return v;
+  const std::string key = "fwd-direct|" + tune_arch() + "|L=" + bank_list(desc->n_banks, desc->L) +
+                          "|K=" + std::to_string(K) + "|n=" + std::to_string(nc);
+  int v = 0;
+  std::string name;
+  float ms = 0.f;
+  if (tune_cache_lookup(key, &name)) v = variant_index(name);
+  const char *env = getenv("PRUNE_AUTOTUNE");
+  if (!v && env && env[0] == '0') return 1;
+  const bool tuned = !v;
+  if (!v) v = time_variants(desc, x, taps, frames, y, stream, &ms);
+  if (!v) return 1;
+  if (tuned) tune_cache_store(key, fb_variant_name(v), ms);
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_n_choice < kMaxChoices) g_choice[g_n_choice++] = {Lmax, K, nc, v};
+  return v;
+}
+
+// A graph's filter banks are tuned at finalize, before any data exists, on
+// a synthetic batch with the graph's own structure: its banks and tap
+// counts, prefix masks of a uniform branch count in a uniform bank, and
+// frame lengths of its rate (log-uniform from min(256, rate) up to the rate
+// when the rate is a per-firing parameter), about 64K samples per CU.
+int choose_variant_graph(uint32_t n_banks, const uint32_t *L, uint32_t K, uint32_t n, bool param) {
+  const int forced = forced_variant();
+  if (forced) return forced;
+  const std::string key = "fwd-graph|" + tune_arch() + "|L=" + bank_list(n_banks, L) + "|K=" +
+                          std::to_string(K) + "|n=" + std::to_string(n) + "|param=" +
+                          std::to_string(param ? 1 : 0);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
   }
+  std::string name;
+  int v = 0;
+  if (tune_cache_lookup(key, &name)) v = variant_index(name);
   const char *env = getenv("PRUNE_AUTOTUNE");
-  if (env && env[0] == '0') return 1;
-  // synthetic problem: 64K samples per CU (16.7M on 256 CUs), long enough
-  // that launch overhead and tail effects do not decide the ranking
-  const uint32_t frames = std::max<uint32_t>(64, (uint32_t)((size_t)ncu() * 65536 / nc));
-  const uint64_t N = (uint64_t)frames * nc;
-  float2 *x = nullptr, *y = nullptr, *t = nullptr;
-  prune_fb_frame *fr = nullptr;
-  int best = 1;
-  if (hipMalloc((void **)&x, N * sizeof(float2)) != hipSuccess) return 1;
-  (void)hipMalloc((void **)&y, N * sizeof(float2));
-  (void)hipMalloc((void **)&t, (size_t)K * Lc * sizeof(float2));
-  (void)hipMalloc((void **)&fr, frames * sizeof(prune_fb_frame));
-  {
-    std::vector<float2> hx(N);
-    uint32_t s = 12345u;
-    for (auto &v : hx) {
-      s = s * 1664525u + 1013904223u;
-      v.x = ((s >> 8) & 0xffff) / 65536.f - 0.5f;
-      s = s * 1664525u + 1013904223u;
-      v.y = ((s >> 8) & 0xffff) / 65536.f - 0.5f;
+  if (!v && env && env[0] == '0') return 1;
+  if (!v) {
+    uint32_t Lmax = 1;
+    for (uint32_t b = 0; b < n_banks; ++b) Lmax = std::max(Lmax, L[b]);
+    const uint64_t target = (uint64_t)ncu() * 65536;
+    std::vector<prune_fb_frame> hf;
+    uint32_t st = 12345u;
+    auto u01 = [&]() {
+      st = st * 1664525u + 1013904223u;
+      return ((st >> 8) & 0xffffff) / 16777216.0;
+    };
+    const double lo = std::log((double)std::min<uint32_t>(256, n)), hi = std::log((double)n);
+    uint64_t N = 0;
+    while (N < target && hf.size() < 65536) {
+      prune_fb_frame f{};
+      f.n = param ? (uint32_t)std::min<double>(n, std::max(1.0, std::rint(std::exp(lo + (hi - lo) * u01()))))
+                  : n;
+      const uint32_t k = 1 + (uint32_t)(u01() * K) % K, bank = (uint32_t)(u01() * n_banks) % n_banks;
+      f.mask = (k >= 32 ? 0xffffffffu : ((1u << k) - 1u)) << (bank * K);
+      f.t0 = (uint32_t)N;
+      hf.push_back(f);
+      N += f.n;
     }
-    (void)hipMemcpy(x, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice);
-    std::vector<float2> ht((size_t)K * Lc, make_float2(0.01f, -0.02f));
-    (void)hipMemcpy(t, ht.data(), ht.size() * sizeof(float2), hipMemcpyHostToDevice);
-    std::vector<prune_fb_frame> hf(frames);
-    for (uint32_t f = 0; f < frames; ++f) {
-      hf[f].stream = 0; hf[f].t0 = f * nc; hf[f].n = nc;
-      hf[f].mask = K >= 32 ? 0xffffffffu : ((1u << K) - 1u); hf[f].route = 0;
-      hf[f].pad[0] = hf[f].pad[1] = hf[f].pad[2] = 0;
+    uint32_t mfl = 1;
+    for (auto &f : hf) mfl = std::max(mfl, f.n);
+    prune_fb_desc d{};
+    d.n_streams = 1; d.n_frames = (uint32_t)hf.size(); d.stream_len = N; d.n_banks = n_banks;
+    d.Kmax = K; d.max_frame_len = mfl;
+    for (uint32_t b = 0; b < n_banks; ++b) d.L[b] = L[b];
+    const size_t nt = (size_t)n_banks * K * Lmax;
+    float2 *x = nullptr, *y = nullptr, *t = nullptr;
+    prune_fb_frame *fr = nullptr;
+    bool ok = hipMalloc((void **)&x, N * sizeof(float2)) == hipSuccess &&
+              hipMalloc((void **)&y, N * sizeof(float2)) == hipSuccess &&
+              hipMalloc((void **)&t, nt * sizeof(float2)) == hipSuccess &&
+              hipMalloc((void **)&fr, hf.size() * sizeof(prune_fb_frame)) == hipSuccess;
+    if (ok) {
+      std::vector<float2> hx(N);
+      for (auto &z : hx) z = make_float2((float)u01() - 0.5f, (float)u01() - 0.5f);
+      std::vector<float2> ht(nt, make_float2(0.01f, -0.02f));
+      ok = hipMemcpy(x, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(t, ht.data(), nt * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(fr, hf.data(), hf.size() * sizeof(prune_fb_frame), hipMemcpyHostToDevice) ==
+               hipSuccess;
     }
-    (void)hipMemcpy(fr, hf.data(), frames * sizeof(prune_fb_frame), hipMemcpyHostToDevice);
-  }
-  prune_fb_desc d{};
-  d.n_streams = 1; d.n_frames = frames; d.stream_len = N; d.n_banks = 1; d.Kmax = K;
-  d.L[0] = Lc; d.max_frame_len = nc;
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  float best_ms = 1e30f;
-  g_tuning = true;
-  for (int v = 1; v <= fb_variant_count(); ++v) {
-    prune_fb_forward_variant(&d, x, t, fr, y, v, nullptr);   // warm-up
-    (void)hipEventRecord(e0, nullptr);
-    for (int r = 0; r < 3; ++r) prune_fb_forward_variant(&d, x, t, fr, y, v, nullptr);
-    (void)hipEventRecord(e1, nullptr);
-    (void)hipEventSynchronize(e1);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = v;
-    }
+    if (ok) v = time_variants(&d, x, t, fr, y, nullptr, &ms);
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (t) (void)hipFree(t);
+    if (fr) (void)hipFree(fr);
+    if (!v) return 1;
+    tune_cache_store(key, fb_variant_name(v), ms);
   }
-  g_tuning = false;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(x); (void)hipFree(y); (void)hipFree(t); (void)hipFree(fr);
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[key] = best;
-  }
-  if (const char *path = getenv("PRUNE_AUTOTUNE_CACHE")) {
-    if (FILE *f = fopen(path, "a")) {
-      fprintf(f, "{\"arch\": \"gfx950\", \"L\": %u, \"K\": %u, \"n\": %u, \"variant\": \"%s\", \"ms\": %.4f}\n",
-              Lc, K, nc, fb_variant_name(best), best_ms);
-      fclose(f);
-    }
-  }
-  return best;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tuned[key] = v;
+  return v;
 }
 
 }  // namespace prune

@@ -29,6 +29,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -548,8 +549,10 @@ static prune_status check_bwd_desc(const prune_fb_desc *d) {
 constexpr int kBwdVariants = 2;   // 1: vector Horner kernel, 2: matrix-core kernels
 static std::atomic<int> g_bwd_forced{0};
 static std::mutex g_bwd_mu;
-static std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int> g_bwd_tuned;
-static int choose_bwd_variant(uint32_t L, uint32_t K, uint32_t n);
+static std::map<std::string, int> g_bwd_tuned;
+static int choose_bwd_variant(const prune_fb_desc *desc, const void *x, const void *taps,
+                              const void *frames, const void *gy, void *gx, void *gtaps,
+                              void *workspace, size_t workspace_bytes, prune_stream_t stream);
 static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x, const void *taps,
                                         const void *frames, const void *gy, void *gx, void *gtaps,
                                         void *workspace, size_t workspace_bytes, int variant,
@@ -575,9 +578,8 @@ prune_status prune_fb_backward(const prune_fb_desc *desc, const void *x, const v
   prune_status st = check_bwd_desc(desc);
   if (st != PRUNE_OK) return st;
   if (!x || !taps || !frames || !gy || (!gx && !gtaps) || !workspace) return PRUNE_E_ARG;
-  uint32_t Lmax = 1;
-  for (uint32_t b = 0; b < desc->n_banks; ++b) Lmax = std::max(Lmax, desc->L[b]);
-  const int v = choose_bwd_variant(Lmax, desc->Kmax, desc->max_frame_len);
+  const int v = choose_bwd_variant(desc, x, taps, frames, gy, gx, gtaps, workspace, workspace_bytes,
+                                   stream);
   return fb_backward_variant(desc, x, taps, frames, gy, gx, gtaps, workspace, workspace_bytes, v,
                              stream);
 }
@@ -598,7 +600,56 @@ const char *prune_bwd_variant_name(int variant) {
 
 prune_status prune_autotune_bwd(uint32_t L, uint32_t K, uint32_t n, int *variant) {
   if (L < 1 || L > PRUNE_MAX_L || K < 1 || K > 10 || n < 1) return PRUNE_E_ARG;
-  const int v = choose_bwd_variant(L, K, n);
+  // a synthetic batch of the shape class: uniform frames of length n,
+  // every branch active, about 16K samples per CU
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t frames = std::max<uint32_t>(64, (uint32_t)((size_t)ncu * 16384 / n));
+  const uint64_t N = (uint64_t)frames * n;
+  prune_fb_desc d{};
+  d.n_streams = 1; d.n_frames = frames; d.stream_len = N; d.n_banks = 1; d.Kmax = K;
+  d.L[0] = L; d.max_frame_len = n;
+  const size_t ws = bwd_layout(d).total;
+  float2 *x = nullptr, *g = nullptr, *gx = nullptr, *t = nullptr, *gt = nullptr;
+  prune_fb_frame *fr = nullptr;
+  void *work = nullptr;
+  bool ok = hipMalloc((void **)&x, N * sizeof(float2)) == hipSuccess &&
+            hipMalloc((void **)&g, N * sizeof(float2)) == hipSuccess &&
+            hipMalloc((void **)&gx, N * sizeof(float2)) == hipSuccess &&
+            hipMalloc((void **)&t, (size_t)K * L * sizeof(float2)) == hipSuccess &&
+            hipMalloc((void **)&gt, (size_t)K * L * sizeof(float2)) == hipSuccess &&
+            hipMalloc((void **)&fr, frames * sizeof(prune_fb_frame)) == hipSuccess &&
+            hipMalloc(&work, ws) == hipSuccess;
+  if (ok) {
+    std::vector<float2> hx(N);
+    uint32_t st = 2468u;
+    for (auto &v : hx) {
+      st = st * 1664525u + 1013904223u;
+      v.x = ((st >> 8) & 0xffff) / 65536.f - 0.5f;
+      st = st * 1664525u + 1013904223u;
+      v.y = ((st >> 8) & 0xffff) / 65536.f - 0.5f;
+    }
+    std::vector<float2> ht((size_t)K * L, make_float2(0.01f, -0.02f));
+    std::vector<prune_fb_frame> hf(frames);
+    for (uint32_t f = 0; f < frames; ++f) {
+      hf[f] = prune_fb_frame{};
+      hf[f].t0 = f * n; hf[f].n = n; hf[f].mask = (1u << K) - 1u;
+    }
+    ok = hipMemcpy(x, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(g, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(t, ht.data(), ht.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(fr, hf.data(), frames * sizeof(prune_fb_frame), hipMemcpyHostToDevice) == hipSuccess;
+  }
+  const int v = ok ? choose_bwd_variant(&d, x, t, fr, g, gx, gt, work, ws, nullptr) : 1;
+  if (x) (void)hipFree(x);
+  if (g) (void)hipFree(g);
+  if (gx) (void)hipFree(gx);
+  if (t) (void)hipFree(t);
+  if (gt) (void)hipFree(gt);
+  if (fr) (void)hipFree(fr);
+  if (work) (void)hipFree(work);
+  if (!ok) return PRUNE_E_HIP;
   if (variant) *variant = v;
   return PRUNE_OK;
 }
@@ -673,83 +724,71 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }
 
-// Time both backward forms on a synthetic batch of the shape class and keep
-// the faster.  Key: (L rounded up to a multiple of 8, K, frame length class).
-static int choose_bwd_variant(uint32_t L, uint32_t K, uint32_t n) {
+// Both backward forms timed on the call's own inputs (the gradients and
+// workspace are rewritten by the call that follows): a warm-up of each,
+// then five rounds launching each form once in turn, each launch timed by
+// its own events; the smaller median wins.  Once per shape class (banks,
+// Kmax, frame-length class, whether grad_x is wanted) and process, unless
+// PRUNE_AUTOTUNE_CACHE already holds a choice for it on this architecture.
+static int choose_bwd_variant(const prune_fb_desc *desc, const void *x, const void *taps,
+                              const void *frames, const void *gy, void *gx, void *gtaps,
+                              void *workspace, size_t workspace_bytes, prune_stream_t stream) {
   const int forced = g_bwd_forced.load();
   if (forced) return forced;
-  const uint32_t Lc = (L + 7) / 8 * 8;
+  const uint32_t n = desc->max_frame_len;
   const uint32_t nc = n >= 8192 ? 8192 : (n >= 2048 ? 2048 : 512);
-  const auto key = std::make_tuple(Lc, K, nc);
+  std::string key = "bwd|" + tune_arch() + "|L=";
+  for (uint32_t b = 0; b < desc->n_banks; ++b) key += (b ? "," : "") + std::to_string(desc->L[b]);
+  key += "|K=" + std::to_string(desc->Kmax) + "|n=" + std::to_string(nc) + "|gx=" + (gx ? "1" : "0");
   {
     std::lock_guard<std::mutex> lk(g_bwd_mu);
     auto it = g_bwd_tuned.find(key);
     if (it != g_bwd_tuned.end()) return it->second;
   }
+  int best = 0;
+  std::string name;
+  if (tune_cache_lookup(key, &name))
+    for (int v = 1; v <= kBwdVariants; ++v)
+      if (name == prune_bwd_variant_name(v)) best = v;
   const char *env = getenv("PRUNE_AUTOTUNE");
-  if (env && env[0] == '0') return 1;
-  int dev = 0, ncu = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const uint32_t frames = std::max<uint32_t>(64, (uint32_t)((size_t)ncu * 16384 / nc));
-  const uint64_t N = (uint64_t)frames * nc;
-  prune_fb_desc d{};
-  d.n_streams = 1; d.n_frames = frames; d.stream_len = N; d.n_banks = 1; d.Kmax = K;
-  d.L[0] = Lc; d.max_frame_len = nc;
-  const size_t ws = bwd_layout(d).total;
-  float2 *x = nullptr, *g = nullptr, *gx = nullptr, *t = nullptr, *gt = nullptr;
-  prune_fb_frame *fr = nullptr;
-  void *work = nullptr;
-  int best = 1;
-  bool ok = hipMalloc((void **)&x, N * sizeof(float2)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&g, N * sizeof(float2)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&gx, N * sizeof(float2)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&t, (size_t)K * Lc * sizeof(float2)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&gt, (size_t)K * Lc * sizeof(float2)) == hipSuccess;
-  ok = ok && hipMalloc((void **)&fr, frames * sizeof(prune_fb_frame)) == hipSuccess;
-  ok = ok && hipMalloc(&work, ws) == hipSuccess;
-  if (ok) {
-    std::vector<float2> hx(N);
-    uint32_t st = 2468u;
-    for (auto &v : hx) {
-      st = st * 1664525u + 1013904223u;
-      v.x = ((st >> 8) & 0xffff) / 65536.f - 0.5f;
-      st = st * 1664525u + 1013904223u;
-      v.y = ((st >> 8) & 0xffff) / 65536.f - 0.5f;
-    }
-    (void)hipMemcpy(x, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice);
-    (void)hipMemcpy(g, hx.data(), N * sizeof(float2), hipMemcpyHostToDevice);
-    std::vector<float2> ht((size_t)K * Lc, make_float2(0.01f, -0.02f));
-    (void)hipMemcpy(t, ht.data(), ht.size() * sizeof(float2), hipMemcpyHostToDevice);
-    std::vector<prune_fb_frame> hf(frames);
-    for (uint32_t f = 0; f < frames; ++f) {
-      hf[f].stream = 0; hf[f].t0 = f * nc; hf[f].n = nc;
-      hf[f].mask = (1u << K) - 1u; hf[f].route = 0;
-      hf[f].pad[0] = hf[f].pad[1] = hf[f].pad[2] = 0;
-    }
-    (void)hipMemcpy(fr, hf.data(), frames * sizeof(prune_fb_frame), hipMemcpyHostToDevice);
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+  if (!best && env && env[0] == '0') return 1;
+  if (!best) {
+    constexpr int kRounds = 5;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[2 * kRounds * kBwdVariants] = {};
+    bool ok = true;
+    for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     float best_ms = 1e30f;
-    for (int v = 1; v <= kBwdVariants; ++v) {
-      fb_backward_variant(&d, x, t, fr, g, gx, gt, work, ws, v, nullptr);   // warm-up
-      (void)hipEventRecord(e0, nullptr);
-      for (int r = 0; r < 3; ++r) fb_backward_variant(&d, x, t, fr, g, gx, gt, work, ws, v, nullptr);
-      (void)hipEventRecord(e1, nullptr);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = v;
-      }
+    if (ok) {
+      for (int v = 1; v <= kBwdVariants; ++v)
+        fb_backward_variant(desc, x, taps, frames, gy, gx, gtaps, workspace, workspace_bytes, v, stream);
+      for (int r = 0; r < kRounds; ++r)
+        for (int v = 1; v <= kBwdVariants; ++v) {
+          hipEvent_t *e = &ev[2 * (r * kBwdVariants + v - 1)];
+          (void)hipEventRecord(e[0], s);
+          fb_backward_variant(desc, x, taps, frames, gy, gx, gtaps, workspace, workspace_bytes, v,
+                              stream);
+          (void)hipEventRecord(e[1], s);
+        }
+      if (hipStreamSynchronize(s) == hipSuccess)
+        for (int v = 1; v <= kBwdVariants; ++v) {
+          float t[kRounds];
+          for (int r = 0; r < kRounds; ++r) {
+            hipEvent_t *e = &ev[2 * (r * kBwdVariants + v - 1)];
+            if (hipEventElapsedTime(&t[r], e[0], e[1]) != hipSuccess) t[r] = 1e30f;
+          }
+          std::sort(t, t + kRounds);
+          if (t[kRounds / 2] < best_ms) {
+            best_ms = t[kRounds / 2];
+            best = v;
+          }
+        }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (!best) return 1;
+    tune_cache_store(key, prune_bwd_variant_name(best), best_ms);
   }
-  (void)hipFree(x); (void)hipFree(g); (void)hipFree(gx); (void)hipFree(t); (void)hipFree(gt);
-  (void)hipFree(fr); (void)hipFree(work);
   std::lock_guard<std::mutex> lk(g_bwd_mu);
   g_bwd_tuned[key] = best;
   return best;

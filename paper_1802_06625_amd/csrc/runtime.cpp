@@ -1410,14 +1410,22 @@ prune_status prune_graph_finalize(prune_graph_t g, uint32_t C) {
       g->Bcap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->Bcap, blocks > pre ? blocks - pre : 1));
     }
   {
-    uint32_t L = 0, K = 1, n = 1;
+    // tuned on the structure of the filter bank with the most work per
+    // sample (first such one): its banks, branch count and input rate
+    const HActor *best = nullptr;
     for (auto &A : g->actors)
-      if (A.kind == PRUNE_FILTERBANK) {
-        L = std::max(L, fb_lmax(A.fb));
-        K = std::max(K, A.fb.Kmax);
-        n = std::max(n, in_atr(g, A));
-      }
-    g->variant = L ? choose_variant(L, K, n) : 1;
+      if (A.kind == PRUNE_FILTERBANK &&
+          (!best || fb_lmax(A.fb) * A.fb.Kmax > fb_lmax(best->fb) * best->fb.Kmax))
+        best = &A;
+    g->variant = 1;
+    if (best) {
+      bool param = false;
+      for (uint32_t p : best->ports)
+        if (g->ports[p].dir == PRUNE_IN && g->ports[p].kind != PRUNE_CPORT)
+          param = (g->ports[p].flags & PRUNE_PORT_PARAM) != 0;
+      const uint32_t n = std::max<uint32_t>(1, in_atr(g, *best) - (best->fb.windowed ? fb_lmax(best->fb) - 1 : 0));
+      g->variant = choose_variant_graph(best->fb.n_banks, best->fb.L, best->fb.Kmax, n, param);
+    }
   }
   g->tile = (uint32_t)fb_variant_tile(g->variant);
   g->fb_grid = g->ncu * 4;   // residency of the J = 8, 256-thread forward kernels per CU

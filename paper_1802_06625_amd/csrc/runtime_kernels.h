@@ -2,6 +2,8 @@
 // the kernel translation units.
 #pragma once
 
+#include <string>
+
 #include "prune_internal.h"
 
 namespace prune {
@@ -114,7 +116,15 @@ void launch_direct_prep(const prune_fb_desc &d, const float2 *x, const float2 *t
                         const prune_fb_frame *frames, float2 *y, uint32_t tile,
                         FbFrameDesc *desc, WorkItem *items, uint32_t *n_items,
                         unsigned int *ticket, uint32_t *err, hipStream_t s);
-int choose_variant(uint32_t L, uint32_t K, uint32_t n);
+// Forward variant for a graph's filter banks (tuned on a synthetic batch of
+// the graph's structure, cached per process and in PRUNE_AUTOTUNE_CACHE).
+int choose_variant_graph(uint32_t n_banks, const uint32_t *L, uint32_t K, uint32_t n, bool param);
+// Persistent autotuning choices (PRUNE_AUTOTUNE_CACHE), keyed by strings
+// that name the kernel family, the architecture and the shape class.
+std::string tune_arch();
+bool tune_cache_lookup(const std::string &key, std::string *choice);
+void tune_cache_store(const std::string &key, const char *choice, double ms);
+void tune_cache_counts(uint32_t *runs, uint32_t *hits);
 // Per-thread kernel timing (prune_timing_enable / prune_last_fb_kernel_ms).
 bool timing_on();
 void timing_restart();

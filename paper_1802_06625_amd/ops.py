@@ -177,6 +177,16 @@ def autotuned_variant(L, K, n):
     return v.value
 
 
+def tuned_variant(x, frames_dev, Kmax, bank_L, max_frame_len):
+    """Forward variant fb_forward uses for this shape class (1-based; 0 when
+    not tuned yet)."""
+    S, N = x.shape
+    d = make_desc(S, N, Kmax, bank_L, frames_dev.shape[0], max_frame_len)
+    v = C.c_int()
+    call("prune_fb_tuned_variant", C.byref(d), C.byref(v))
+    return v.value
+
+
 def set_bwd_variant(v):
     """0: autotuned, 1: vector kernel, 2: matrix-core kernels."""
     call("prune_set_bwd_variant", int(v))
