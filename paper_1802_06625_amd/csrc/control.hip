@@ -854,7 +854,16 @@ void launch_clear(uint32_t *p, uint32_t n, hipStream_t s) {
 
 namespace prune {
 
-__global__ __launch_bounds__(256) void k_batch_decode(CtrlArgs c, BatchArgs b) {
+// One wave per workgroup; each thread keeps the per-FIFO token counts of its
+// iteration in LDS (a row of kMaxCompFifos + 1 words, an odd stride, so the
+// lanes of an access hit distinct banks), which keeps the kernel at a few
+// dozen registers: it runs beside the persistent filter-bank kernel of the
+// previous batch in the room that kernel leaves free.
+constexpr int kDecodeWG = 64;
+__global__ __launch_bounds__(kDecodeWG) void k_batch_decode(CtrlArgs c, BatchArgs b) {
+  __shared__ uint32_t s_wrote[kDecodeWG][kMaxCompFifos + 1];
+  __shared__ uint32_t s_tmask[kDecodeWG][kMaxCompFifos + 1];
+  __shared__ uint32_t s_trate[kDecodeWG][kMaxCompFifos + 1];
   const uint32_t comp = blockIdx.y;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   // per-level counters and work tickets start at zero for the later phases
@@ -864,9 +873,7 @@ __global__ __launch_bounds__(256) void k_batch_decode(CtrlArgs c, BatchArgs b) {
   }
   if (i >= c.B) return;
   const uint32_t Bc = c.Bcap;
-  uint32_t wrote[kMaxCompFifos];
-  uint32_t tmask[kMaxCompFifos], trate[kMaxCompFifos];
-#pragma unroll
+  uint32_t *wrote = s_wrote[threadIdx.x], *tmask = s_tmask[threadIdx.x], *trate = s_trate[threadIdx.x];
   for (int k = 0; k < kMaxCompFifos; ++k) { wrote[k] = 0; tmask[k] = 0; trate[k] = 0; }
   for (uint32_t ka = c.comp_off[comp]; ka < c.comp_off[comp + 1]; ++ka) {
     const uint32_t a = c.comp_actors[ka];
@@ -1394,7 +1401,8 @@ __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
 
 void launch_batch(const CtrlArgs &c, const BatchArgs &b, uint32_t n_comp, uint32_t n_actors,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_decode, dim3((c.B + 255) / 256, n_comp), dim3(256), 0, s, c, b);
+  hipLaunchKernelGGL(k_batch_decode, dim3((c.B + kDecodeWG - 1) / kDecodeWG, n_comp), dim3(kDecodeWG), 0,
+                     s, c, b);
   hipLaunchKernelGGL(k_batch_scan, dim3(n_actors, kScanFixed + b.max_acc), dim3(kScanNT), 0, s, c, b);
   hipLaunchKernelGGL(k_batch_emit, dim3((c.B + 63) / 64, n_actors), dim3(64), 0, s, c, b);
 }

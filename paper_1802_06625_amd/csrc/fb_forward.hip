@@ -325,12 +325,11 @@ static const FbVariant kVariants[] = {
     {"valu_horner_J4_WG256_w3", 4 * 256, 256, launch_fwd<4, 256, 3>},
     {"valu_horner_J8_WG128_w2", 8 * 128, 128, launch_fwd<8, 128, 2>},
     {"valu_horner_J4_WG128_w4", 4 * 128, 128, launch_fwd<4, 128, 4>},
-    {"valu_horner_J8_WG256_g8", 8 * 256, 256, launch_fwd<8, 256, 1, 8, false>},
+    {"valu_horner_J8_WG256_p2", 8 * 256, 256, launch_fwd<8, 256, 1, 2, true>},
     // matrix-core block-Toeplitz kernels: NT result tiles per wave, NW waves
     {"mfma_toeplitz_NT4_W4", 4 * 256 * 4, 256, launch_fb_mfma<4, 4>},
     {"mfma_toeplitz_NT2_W4", 2 * 256 * 4, 256, launch_fb_mfma<2, 4>},
     {"mfma_toeplitz_NT4_W2", 4 * 256 * 2, 128, launch_fb_mfma<4, 2>},
-    {"valu_horner_J8_WG256_p2", 8 * 256, 256, launch_fwd<8, 256, 1, 2, true>},
 };
 
 int fb_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }

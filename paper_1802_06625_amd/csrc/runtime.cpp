@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -32,6 +33,7 @@ thread_local float g_fb_ms = 0.f;
 thread_local uint32_t g_fb_launches = 0;
 thread_local bool g_timing = false;
 std::atomic<bool> g_pipeline{true};   // batched firing: bookkeeping on a side stream
+
 thread_local std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 int g_variant_forced = 0;
 }  // namespace
@@ -181,6 +183,9 @@ struct prune_graph {
   unsigned long long *d_trace_count = nullptr;
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::map<uint64_t, hipGraph_t> graph_defs;
+  // pipelined graph form: [set parity][0 bookkeeping, 1 data kernels]
+  std::map<uint64_t, hipGraphExec_t> pgraphs[2][2];
+  std::map<uint64_t, hipGraph_t> pgraph_defs[2][2];
   hipStream_t capture_stream = nullptr;
   int variant = 1;
   uint32_t tile = 2048;
@@ -212,6 +217,11 @@ prune_graph::~prune_graph() {
   if (side_stream) (void)hipStreamDestroy(side_stream);
   for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto &kv : graph_defs) (void)hipGraphDestroy(kv.second);
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 2; ++k) {
+      for (auto &kv : pgraphs[p][k]) (void)hipGraphExecDestroy(kv.second);
+      for (auto &kv : pgraph_defs[p][k]) (void)hipGraphDestroy(kv.second);
+    }
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
   for (void *p : owned) (void)hipFree(p);
   for (auto &a : actors)
@@ -1083,6 +1093,8 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
       launch_control(c, g->n_comp, st);
     }
   };
+  // the next batch's bookkeeping is issued beside this batch's data kernels
+  const bool pipelined = g->fast_batch && g->side_stream && g_pipeline;
   auto data = [&](hipStream_t st) {
     CtrlArgs c = make_args(g, B);
     for (uint32_t l = 0; l < g->n_levels; ++l) {
@@ -1100,13 +1112,43 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
     bookkeeping(st);
     data(st);
   };
-  if (!use_graph && g->fast_batch && g->side_stream && g_pipeline) {
+  const uint64_t key = (uint64_t)B | (cmask << 20) | (gmask << 42);
+  // capture fn's launches once into a graph kept in (execs, defs) under key
+  auto captured = [&](std::map<uint64_t, hipGraphExec_t> &execs, std::map<uint64_t, hipGraph_t> &defs,
+                      const std::function<void(hipStream_t)> &fn, hipGraphExec_t *out) -> prune_status {
+    auto it = execs.find(key);
+    if (it == execs.end()) {
+      if (!g->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+      HIPCHECK(hipStreamSynchronize(s));
+      const bool was = g_timing;
+      g_timing = false;
+      HIPCHECK(hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeRelaxed));
+      fn(g->capture_stream);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(g->capture_stream, &graph);
+      g_timing = was;
+      HIPCHECK(e);
+      hipGraphExec_t exec = nullptr;
+      HIPCHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      defs[key] = graph;
+      it = execs.emplace(key, exec).first;
+    }
+    *out = it->second;
+    return PRUNE_OK;
+  };
+  if (pipelined) {
     // pipelined: bookkeeping on the side stream into set p, data kernels on
     // the caller's stream once it is done; set p is reused only after the
-    // data kernels of the batch that last used it
+    // data kernels of the batch that last used it.  The graph form replays
+    // the same two parts as two captured graphs per set, in the same order.
     const uint32_t p = g->parity;
     use_set(g, p);
     hipStream_t b = g->side_stream;
+    hipGraphExec_t gbk = nullptr, gdata = nullptr;
+    if (use_graph) {
+      TRY(captured(g->pgraphs[p][0], g->pgraph_defs[p][0], bookkeeping, &gbk));
+      TRY(captured(g->pgraphs[p][1], g->pgraph_defs[p][1], data, &gdata));
+    }
     if (g->need_sync) {
       HIPCHECK(hipEventRecord(g->ev_sync, s));
       HIPCHECK(hipStreamWaitEvent(b, g->ev_sync, 0));
@@ -1114,10 +1156,16 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
     } else if (g->done_valid[p]) {
       HIPCHECK(hipStreamWaitEvent(b, g->ev_done[p], 0));
     }
-    bookkeeping(b);
+    if (use_graph)
+      HIPCHECK(hipGraphLaunch(gbk, b));
+    else
+      bookkeeping(b);
     HIPCHECK(hipEventRecord(g->ev_emit[p], b));
     HIPCHECK(hipStreamWaitEvent(s, g->ev_emit[p], 0));
-    data(s);
+    if (use_graph)
+      HIPCHECK(hipGraphLaunch(gdata, s));
+    else
+      data(s);
     HIPCHECK(hipEventRecord(g->ev_done[p], s));
     g->done_valid[p] = true;
     g->parity ^= 1u;
@@ -1132,24 +1180,9 @@ prune_status run_batch(prune_graph *g, uint32_t B, hipStream_t s, bool use_graph
     HIPCHECK(hipGetLastError());
     return PRUNE_OK;
   }
-  const uint64_t key = (uint64_t)B | (cmask << 20) | (gmask << 42);
-  auto it = g->graphs.find(key);
-  if (it == g->graphs.end()) {
-    if (!g->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
-    HIPCHECK(hipStreamSynchronize(s));
-    const bool was = g_timing;
-    g_timing = false;
-    HIPCHECK(hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeRelaxed));
-    enqueue(g->capture_stream);
-    hipGraph_t graph = nullptr;
-    HIPCHECK(hipStreamEndCapture(g->capture_stream, &graph));
-    g_timing = was;
-    hipGraphExec_t exec = nullptr;
-    HIPCHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    g->graph_defs[key] = graph;
-    it = g->graphs.emplace(key, exec).first;
-  }
-  HIPCHECK(hipGraphLaunch(it->second, s));
+  hipGraphExec_t exec = nullptr;
+  TRY(captured(g->graphs, g->graph_defs, enqueue, &exec));
+  HIPCHECK(hipGraphLaunch(exec, s));
   return PRUNE_OK;
 }
 
@@ -1785,6 +1818,13 @@ prune_status prune_trace_enable(prune_graph_t g, size_t max_records) {
   for (auto &kv : g->graph_defs) (void)hipGraphDestroy(kv.second);
   g->graphs.clear();
   g->graph_defs.clear();
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 2; ++k) {
+      for (auto &kv : g->pgraphs[p][k]) (void)hipGraphExecDestroy(kv.second);
+      for (auto &kv : g->pgraph_defs[p][k]) (void)hipGraphDestroy(kv.second);
+      g->pgraphs[p][k].clear();
+      g->pgraph_defs[p][k].clear();
+    }
   if (!max_records) return PRUNE_OK;
   HIPCHECK(hipMalloc((void **)&g->d_trace, max_records * sizeof(prune_trace_record)));
   HIPCHECK(hipMalloc((void **)&g->d_trace_count, sizeof(unsigned long long)));
