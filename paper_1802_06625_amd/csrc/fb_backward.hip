@@ -43,24 +43,32 @@ namespace prune {
 constexpr int kBJ = 4;          // inputs per lane for grad_x
 constexpr int kBWG = 256;
 static_assert(kBJ * kBWG == kBT, "vector backward tile");
-constexpr int kRedG = 64;        // first-stage chunks per stream
 
 __device__ __forceinline__ int bidx(int i) { return i + (i >> 3); }
+
+// Per-stream sums of covered samples are kept in LDS for up to this many
+// streams (global atomics beyond).
+constexpr uint32_t kPrepCovLds = 1024;
 
 __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2 *x,
                                                    const float2 *taps, const prune_fb_frame *fr,
                                                    const float2 *g, float2 *gx, BwdFrame *bf,
                                                    WorkItem *items, uint32_t *n_items,
                                                    uint32_t *s_begin, uint32_t *s_end,
-                                                   unsigned long long *cov) {
+                                                   unsigned long long *cov, uint32_t *sfirst) {
   __shared__ uint32_t sm[32];
   __shared__ uint32_t s_carry;
   __shared__ uint32_t s_pre[1024], s_tl[1024];
+  __shared__ unsigned long long s_cov[kPrepCovLds];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const size_t tstride = (size_t)d.n_banks * d.Kmax * Lmax;
-  for (uint32_t s = tid; s < d.n_streams; s += nt) { s_begin[s] = 0; s_end[s] = 0; cov[s] = 0ull; }
+  const bool lds_cov = d.n_streams <= kPrepCovLds;
+  for (uint32_t s = tid; s < d.n_streams; s += nt) {
+    s_begin[s] = 0; s_end[s] = 0; cov[s] = 0ull; sfirst[s] = 0xffffffffu;
+    if (lds_cov) s_cov[s] = 0ull;
+  }
   if (tid == 0) s_carry = 0;
   __syncthreads();
   for (uint32_t base = 0; base < d.n_frames; base += nt) {
@@ -79,7 +87,11 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
       b.pad0 = b.pad1 = b.pad2 = 0;
       bf[f] = b;
       tiles = (b.n + kBT - 1) / kBT;
-      if (b.n) atomicAdd(&cov[q.stream], (unsigned long long)b.n);   // samples covered
+      if (b.n) {   // samples covered
+        if (lds_cov) atomicAdd(&s_cov[q.stream], (unsigned long long)b.n);
+        else atomicAdd(&cov[q.stream], (unsigned long long)b.n);
+      }
+      if (q.stream < d.n_streams && (f == 0 || fr[f - 1].stream != q.stream)) sfirst[q.stream] = f;
     }
     uint32_t v = tiles;
     for (int o = 1; o < 64; o <<= 1) {
@@ -126,6 +138,9 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
     n_items[1] = 0u;   // work tickets of the matrix-core adjoint kernels
     n_items[2] = 0u;
   }
+  __syncthreads();
+  if (lds_cov)
+    for (uint32_t s = tid; s < d.n_streams; s += nt) cov[s] = s_cov[s];
 }
 
 // Zero grad_x of streams whose frames do not cover every sample (the
@@ -439,13 +454,8 @@ __global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_
   out = make_float2(out.x + acc.x, out.y + acc.y);
 }
 
-// Two-stage fixed-order float64 reduction of the tile partials of each
-// stream.  Stage 1: workgroup (stream s, block of 64 entries, chunk c) sums
-// the stream's tiles of chunk c; its 4 x 64 threads take tiles q, q+4, ... of
-// the chunk and their sums are added in q order.  Stage 2: workgroup
-// (s, entry block) adds the chunk sums the same way.  The order of every sum
-// depends only on the item list, so results are reproducible.
-constexpr int kRedQ = 4;          // sub-sums per entry
+// The two reduction stages (bwd_common.h) as kernels: workgroup (stream,
+// entry block, chunk) and (stream, entry block).
 __global__ __launch_bounds__(256) void k_bwd_reduce1(prune_fb_desc d, const float2 *__restrict__ partial,
                                                      const uint32_t *__restrict__ s_begin,
                                                      const uint32_t *__restrict__ s_end,
@@ -453,31 +463,8 @@ __global__ __launch_bounds__(256) void k_bwd_reduce1(prune_fb_desc d, const floa
   __shared__ double2 red[kRedQ][64];
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
-  const uint32_t E = d.n_banks * d.Kmax * Lmax;
-  const uint32_t s = blockIdx.x, eb = blockIdx.y, c = blockIdx.z;
-  const uint32_t el = threadIdx.x & 63, q = threadIdx.x >> 6, e = eb * 64 + el;
-  const uint32_t b0 = s_begin[s], b1 = s_end[s];
-  const uint32_t per = (b1 - b0 + kRedG - 1) / kRedG;
-  const uint32_t lo = min(b1, b0 + c * per), hi = min(b1, lo + per);
-  double sr = 0.0, si = 0.0;
-  if (e < E) {
-    for (uint32_t t = lo + q; t < hi; t += kRedQ) {
-      const float2 v = partial[(size_t)t * E + e];
-      sr += v.x;
-      si += v.y;
-    }
-  }
-  red[q][el] = make_double2(sr, si);
-  __syncthreads();
-  if (q == 0 && e < E) {
-    double2 a = red[0][el];
-#pragma unroll
-    for (int k = 1; k < kRedQ; ++k) {
-      a.x += red[k][el].x;
-      a.y += red[k][el].y;
-    }
-    part2[((size_t)s * kRedG + c) * E + e] = a;
-  }
+  const uint32_t E = d.n_banks * d.Kmax * Lmax, s = blockIdx.x;
+  red_chunk_block(E, partial, s_begin[s], s_end[s], s, blockIdx.z, blockIdx.y, part2, red);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const double2 *__restrict__ part2,
@@ -486,31 +473,11 @@ __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const doub
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const uint32_t E = d.n_banks * d.Kmax * Lmax;
-  const uint32_t s = blockIdx.x, eb = blockIdx.y;
-  const uint32_t el = threadIdx.x & 63, q = threadIdx.x >> 6, e = eb * 64 + el;
-  double sr = 0.0, si = 0.0;
-  if (e < E) {
-    for (uint32_t c = q; c < (uint32_t)kRedG; c += kRedQ) {
-      const double2 v = part2[((size_t)s * kRedG + c) * E + e];
-      sr += v.x;
-      si += v.y;
-    }
-  }
-  red[q][el] = make_double2(sr, si);
-  __syncthreads();
-  if (q == 0 && e < E) {
-    double2 a = red[0][el];
-#pragma unroll
-    for (int k = 1; k < kRedQ; ++k) {
-      a.x += red[k][el].x;
-      a.y += red[k][el].y;
-    }
-    gtaps[(size_t)s * E + e] = make_float2((float)a.x, (float)a.y);
-  }
+  red_stream_block(E, part2, blockIdx.x, kRedG, blockIdx.y, gtaps, red);   // stage 1 wrote every chunk
 }
 
 struct BwdLayout {
-  size_t frames, items, partial, part2, hg, sbeg, send, cov, cnt, total;
+  size_t frames, items, partial, part2, hg, sbeg, send, cov, sfirst, cnt, total;
   uint32_t max_items, E, H;
 };
 
@@ -532,6 +499,7 @@ static BwdLayout bwd_layout(const prune_fb_desc &d) {
   L.sbeg = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
   L.send = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
   L.cov = o; o = al(o + (size_t)d.n_streams * sizeof(unsigned long long));
+  L.sfirst = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
   L.cnt = o; o = al(o + 16);
   L.total = o;
   return L;
@@ -676,6 +644,7 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   uint32_t *sb = (uint32_t *)(w + L.sbeg), *se = (uint32_t *)(w + L.send);
   uint32_t *cnt = (uint32_t *)(w + L.cnt);
   unsigned long long *cov = (unsigned long long *)(w + L.cov);
+  uint32_t *sfirst = (uint32_t *)(w + L.sfirst);
   const prune_fb_desc d = *desc;
   if (d.n_frames == 0) {
     if (gx && hipMemsetAsync(gx, 0, (size_t)d.n_streams * d.stream_len * sizeof(float2), s) != hipSuccess)
@@ -684,25 +653,28 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
       return PRUNE_E_HIP;
     return PRUNE_OK;
   }
+  // Without grad_x only the matrix-core grad_h kernel runs (the vector
+  // kernel computes both gradients in one pass).
+  const bool mfma = variant == 2 || !gx;
   hipLaunchKernelGGL(k_bwd_prep, dim3(1), dim3(1024), 0, s, d, (const float2 *)x, (const float2 *)taps,
                      (const prune_fb_frame *)frames, (const float2 *)gy, (float2 *)gx, bf, items, cnt,
-                     sb, se, cov);
-  // grad_x starts as zero outside the frames' coverage
-  if (gx) hipLaunchKernelGGL(k_bwd_gapfill, dim3(d.n_streams, 64), dim3(256), 0, s, d, cov, (float2 *)gx);
+                     sb, se, cov, sfirst);
+  // grad_x starts as zero outside the frames' coverage (the matrix-core
+  // grad_x kernel zeroes those samples itself)
+  if (gx && !mfma)
+    hipLaunchKernelGGL(k_bwd_gapfill, dim3(d.n_streams, 64), dim3(256), 0, s, d, cov, (float2 *)gx);
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
-  // Without grad_x only the matrix-core grad_h kernel runs (the vector
-  // kernel computes both gradients in one pass).
-  const bool mfma = variant == 2 || !gx;
   if (mfma) {
     // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids of
     // 3 and 2 workgroups per CU, the fastest measured (at their register use
     // the kernels keep 2 and 1 workgroups resident per CU)
     if (gx)
       launch_bwd_gu_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg,
-                         std::min<uint32_t>(L.max_items + d.n_frames, (uint32_t)ncu * 3), s);
+                         std::min<uint32_t>(L.max_items + d.n_frames, (uint32_t)ncu * 3), sfirst,
+                         (float2 *)gx, s);
     if (gtaps)
       launch_bwd_gh_mfma(d, bf, items, cnt, (unsigned int *)(cnt + 2), partial, L.max_items,
                          (uint32_t)ncu * 2, s);

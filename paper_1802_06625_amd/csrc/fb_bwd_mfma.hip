@@ -25,7 +25,10 @@
 //    partial is deterministic, and the per-stream float64 reduction of the
 //    partials is shared with the vector kernel.
 // Halo contributions (inputs before a frame that its outputs read) are
-// added by the same halo/fix kernels as for the vector form.
+// added by the same fix-up kernel as for the vector form, and the tile
+// partials of grad_h by the same reduction kernels.  The grad_x kernel
+// zeroes the samples outside every frame after its items (no separate gap
+// kernel).
 #include <algorithm>
 
 #include "bwd_common.h"
@@ -94,7 +97,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
                                                     const WorkItem *__restrict__ items,
                                                     const uint32_t *__restrict__ n_items,
                                                     unsigned int *__restrict__ ticket,
-                                                    float2 *__restrict__ hg) {
+                                                    float2 *__restrict__ hg,
+                                                    const uint32_t *__restrict__ sfirst,
+                                                    float2 *__restrict__ gxs) {
   // G window: index k holds g at tile position k; the last one read is
   // 256*3 + 16*15 + 3 + 4*(S-1) <= kBT + L + 1.
   constexpr int WN = kBT + PRUNE_MAX_L + 2;
@@ -241,6 +246,33 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
       }
     }
     __syncthreads();   // s_g and s_h are rewritten by the next item
+  }
+  // Samples outside every frame get a zero gradient: workgroup k takes frames
+  // k, k + grid, ... and zeroes the gap after each (up to the next frame of
+  // its stream or the stream's end) and, for a stream's first frame, the
+  // samples before it; then streams without frames.  Frame samples are
+  // written by the items above only, so the two never touch one sample.
+  // (Positions are clamped to the stream: a frame out of range has n = 0.)
+  if (!sfirst) return;
+  const uint64_t N = d.stream_len;
+  for (uint32_t f = blockIdx.x; f < d.n_frames; f += gridDim.x) {
+    const BwdFrame F = bf[f];
+    if (F.stream >= d.n_streams) continue;
+    float2 *row = gxs + (size_t)F.stream * N;
+    const uint64_t end = min((uint64_t)F.t0 + F.n, N);
+    uint64_t nxt = N;
+    if (f + 1 < d.n_frames) {
+      const BwdFrame G = bf[f + 1];
+      if (G.stream == F.stream) nxt = min((uint64_t)G.t0, N);
+    }
+    for (uint64_t q = end + t; q < nxt; q += kWG) row[q] = make_float2(0.f, 0.f);
+    if (sfirst[F.stream] == f)
+      for (uint64_t q = t; q < min((uint64_t)F.t0, N); q += kWG) row[q] = make_float2(0.f, 0.f);
+  }
+  for (uint32_t st = blockIdx.x; st < d.n_streams; st += gridDim.x) {
+    if (sfirst[st] != 0xffffffffu) continue;
+    float2 *row = gxs + (size_t)st * d.stream_len;
+    for (uint64_t q = t; q < d.stream_len; q += kWG) row[q] = make_float2(0.f, 0.f);
   }
 }
 
@@ -472,8 +504,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
 
 void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
                         const uint32_t *n_items, unsigned int *ticket, float2 *hg, uint32_t grid,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_bwd_gu_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, ticket, hg);
+                        const uint32_t *sfirst, float2 *gx, hipStream_t s) {
+  hipLaunchKernelGGL(k_bwd_gu_mfma, dim3(grid), dim3(kWG), 0, s, d, bf, items, n_items, ticket, hg,
+                     sfirst, gx);
 }
 
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,

@@ -9,6 +9,7 @@ import synth
 from oracle import fit
 from oracle.filterbank import fb_stream_adjoint
 from oracle.graphs import stream_frames
+from paper_1802_06625_amd import _lib as L
 from paper_1802_06625_amd import ops
 
 from gpu_util import TOL, announce, rel_l2
@@ -355,3 +356,57 @@ def test_backward_tile_runs(run, form):
         rx, rt = fb_stream_adjoint(x[s], ref, taps[s], bank_L, Kmax, gy[s])
         assert rel_l2(gx[s], rx) <= TOL, (s, rel_l2(gx[s], rx))
         assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
+
+
+@pytest.mark.parametrize("want", [(True, True), (False, True)])
+@pytest.mark.parametrize("form", BWD_FORMS)
+def test_backward_ignores_workspace_and_output_contents(form, want):
+    """The adjoint writes every element of its outputs and never reads stale
+    workspace: with the workspace and the outputs filled with NaN bytes, two
+    calls in a row (uneven frames over three banks, gaps between frames, a
+    stream without frames, fewer tiles than reduction chunks) still match
+    the oracle."""
+    want_gx, want_gt = want
+    announce(f"backward with NaN-filled workspace form {form} want {want}")
+    wl = synth.make("C3", n_frames=8, n_max=3000, n_streams=1, cotangent=True)
+    N = int(wl.x.shape[1])
+    rows, t0 = [], 5
+    for (a, n, m, r) in stream_frames(wl, 0):
+        if t0 + n > N:
+            break
+        rows.append((0, t0, n, m, r))
+        t0 += n + 7          # a gap after every frame
+    S = 3                    # stream 1 has no frames; stream 2 repeats stream 0's frames
+    x = np.zeros((S, N), np.complex64)
+    gy = np.zeros((S, N), np.complex64)
+    x[0], x[2] = wl.x[0], wl.x[0][::-1]
+    gy[0], gy[2] = wl.gy[0], wl.gy[0][::-1]
+    taps = np.stack([wl.taps[0]] * S)
+    rows = rows + [(2,) + r[1:] for r in rows]
+    fr = ops.frame_table(rows)
+    mfl = max(r[2] for r in rows)
+    xd, td, gd = torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(), torch.from_numpy(gy).cuda()
+    d = ops.make_desc(S, N, wl.Kmax, wl.bank_L, len(rows), mfl)
+    ws = L.C.c_size_t()
+    L.call("prune_fb_workspace_bytes", L.C.byref(d), L.C.byref(ws))
+    work = torch.full((ws.value,), 0xFF, dtype=torch.uint8, device="cuda")
+    ops.set_bwd_variant(form)
+    try:
+        for _ in range(2):
+            gx = torch.full_like(xd, complex(float("nan"), float("nan"))) if want_gx else None
+            gt = torch.full_like(td, complex(float("nan"), float("nan")))
+            gx, gt = ops.fb_backward(xd, td, fr, gd, wl.Kmax, wl.bank_L, mfl, gx=gx, gt=gt, work=work,
+                                     want_gx=want_gx, want_gt=want_gt)
+            torch.cuda.synchronize()
+            gxh = gx.cpu().numpy() if want_gx else None
+            gth = gt.cpu().numpy()
+            for s in range(S):
+                fs = [(a, n, m, r) for (ss, a, n, m, r) in rows if ss == s]
+                rx, rt = fb_stream_adjoint(x[s], fs, taps[s], wl.bank_L, wl.Kmax, gy[s])
+                if want_gx:
+                    assert np.all(np.isfinite(gxh[s])), s
+                    assert rel_l2(gxh[s], rx) <= TOL, (s, rel_l2(gxh[s], rx))
+                assert np.all(np.isfinite(gth[s])), s
+                assert rel_l2(gth[s], rt) <= TOL if np.any(rt) else np.all(gth[s] == 0), s
+    finally:
+        ops.set_bwd_variant(0)
