@@ -679,6 +679,15 @@ prune_status prune_rule_config_token(uint32_t mode, uint32_t Kmax, const prune_s
 const char *prune_status_string(prune_status s);
 const char *prune_last_error(void);
 
+/* ---- build ----------------------------------------------------------------- */
+/* Flags of the loaded library.  PRUNE_BUILD_DEBUG: a PRUNE_DEBUG build, whose
+ * bookkeeping kernels check every FIFO after each counter update: the block
+ * state is one the blocking rules reach, the token occupancy stays within
+ * Eq. 2's capacity (Sec. IV), and no access or token counter goes back.  A
+ * failed check makes the next prune_graph_sync return E_RULE. */
+#define PRUNE_BUILD_DEBUG 1u
+uint32_t prune_build_flags(void);
+
 #ifdef __cplusplus
 }
 #endif

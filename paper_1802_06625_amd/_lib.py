@@ -10,7 +10,11 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libprune_hip.so")
+# PRUNE_DEBUG_LIBRARY=1 loads the PRUNE_DEBUG build, whose bookkeeping
+# kernels check the FIFO invariants after every counter update
+DEBUG_LIBRARY = os.environ.get("PRUNE_DEBUG_LIBRARY", "0") not in ("", "0")
+LIB_PATH = os.path.join(HERE, "libprune_hip_debug.so" if DEBUG_LIBRARY else "libprune_hip.so")
+BUILD_DEBUG = 1
 
 # ---- enums (mirror include/prune.h) ---------------------------------------
 OK = 0
@@ -146,6 +150,7 @@ SIGNATURES = [
     ("prune_probe_ceiling", _ST, [C.c_int, C.c_uint32, C.c_uint64, C.c_uint32,
                                   C.POINTER(ProbeResult)]),
     ("prune_status_string", C.c_char_p, [_ST]),
+    ("prune_build_flags", C.c_uint32, []),
     ("prune_last_error", C.c_char_p, []),
 ]
 
@@ -160,12 +165,16 @@ _lib = None
 
 
 def lib():
-    """Load libprune_hip.so (built in-tree by __graft_entry__.build())."""
+    """Load libprune_hip.so, or its debug build with PRUNE_DEBUG_LIBRARY=1
+    (both built in-tree by __graft_entry__.build())."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(the HIP library is required; there is no fallback)")
+        # torch's HIP runtime first: the library then binds to the same one,
+        # so torch's device memory and stream handles are valid in it
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             fn = getattr(L, name)

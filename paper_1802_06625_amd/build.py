@@ -3,7 +3,10 @@
 Every translation unit under csrc/ is compiled as HIP for gfx950 with
 packed-FP32 instructions disabled (-target-feature -packed-fp32-ops) and
 matrix-core accumulators selected in VGPR form, then linked into
-paper_1802_06625_amd/libprune_hip.so.
+paper_1802_06625_amd/libprune_hip.so.  A second library,
+libprune_hip_debug.so, is built from the same sources with PRUNE_DEBUG
+defined: its bookkeeping kernels check the FIFO invariants after every
+counter update.
 """
 from __future__ import annotations
 
@@ -18,6 +21,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libprune_hip.so")
+OUT_DEBUG = os.path.join(HERE, "libprune_hip_debug.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 ARCH = os.environ.get("PRUNE_OFFLOAD_ARCH", "gfx950")
@@ -44,9 +48,10 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc(), "-x", "hip", "-c", src, "-o", obj] + FLAGS
+def _compile(src: str, verbose: bool, debug: bool) -> str:
+    out_dir = os.path.join(BUILD_DIR, "debug") if debug else BUILD_DIR
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [hipcc(), "-x", "hip", "-c", src, "-o", obj] + FLAGS + (["-DPRUNE_DEBUG"] if debug else [])
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,18 +65,26 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sources()
-    jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = OUT + ".tmp"
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False, debug: bool = True) -> str:
+    """Compile and link libprune_hip.so and, with debug, libprune_hip_debug.so."""
+    os.makedirs(os.path.join(BUILD_DIR, "debug"), exist_ok=True)
+    srcs = sources()
+    kinds = [False, True] if debug else [False]
+    jobs = [(s, d) for d in kinds for s in srcs]
+    with cf.ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:
+        objs = list(ex.map(lambda j: _compile(j[0], verbose, j[1]), jobs))
+    _link(objs[:len(srcs)], OUT)
+    if debug:
+        _link(objs[len(srcs):], OUT_DEBUG)
     return OUT
 
 

@@ -253,6 +253,7 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
         carry += tot;
       }
       if (tid == 0) {
+        const uint64_t n0 = is_in ? f.reads : f.writes, t0 = is_in ? f.tokens_read : f.tokens_written;
         if (is_in) {
           f.reads += carry;
           f.tokens_read += toks;
@@ -262,6 +263,10 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
           const uint64_t occ = f.Q + f.tokens_written - f.tokens_read;
           if (occ > f.max_occ) f.max_occ = occ;
         }
+        PRUNE_DEBUG_CHECK(fifo_advance_ok(f.r, n0, t0, is_in ? f.reads : f.writes,
+                                          is_in ? f.tokens_read : f.tokens_written) &&
+                              fifo_counters_ok(f.r, f.Q, f.C, f.writes, f.reads, f.tokens_written, f.tokens_read),
+                          c.err);
       }
       __syncthreads();
       if (is_in) { ++in_slot; break; }
@@ -278,7 +283,12 @@ __device__ void actor_phase(const CtrlArgs &c, uint32_t a, uint32_t *sm32,
       trace_push(c, 1, a, 0u, R[i].firing, R[i].mask, R[i].rate, R[i].bitmap);
     }
     __syncthreads();
-    if (tid == 0) { f.reads += B; f.tokens_read += B; }
+    if (tid == 0) {
+      f.reads += B;
+      f.tokens_read += B;
+      PRUNE_DEBUG_CHECK(fifo_counters_ok(f.r, f.Q, f.C, f.writes, f.reads, f.tokens_written, f.tokens_read),
+                        c.err);
+    }
   }
   for (uint32_t i = tid; i < B; i += nt) R[i].n_io = out_slot;
   __syncthreads();
@@ -1110,12 +1120,16 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
       // workgroup updates these fields
       if (ac.dir == PRUNE_IN) {
         b.s_base[k2] = f.reads;
+        const uint64_t t0 = f.tokens_read;
         f.reads += nacc;
         f.tokens_read += toks;
+        PRUNE_DEBUG_CHECK(fifo_advance_ok(f.r, b.s_base[k2], t0, f.reads, f.tokens_read), c.err);
       } else {
         b.s_base[k2] = f.writes;
+        const uint64_t t0 = f.tokens_written;
         f.writes += nacc;
         f.tokens_written += toks;
+        PRUNE_DEBUG_CHECK(fifo_advance_ok(f.r, b.s_base[k2], t0, f.writes, f.tokens_written), c.err);
         // occupancy with all of this batch's tokens written, before its reads
         const uint64_t occ = f.Q + f.tokens_written - b.s_rsnap[ac.fifo];
         if (occ > f.max_occ) f.max_occ = occ;
@@ -1235,6 +1249,19 @@ __device__ inline const float2 *batch_halo(const CtrlArgs &c, const BatchArgs &b
 
 __global__ __launch_bounds__(64) void k_batch_emit(CtrlArgs c, BatchArgs b) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kDebugBuild && blockIdx.x == 0 && blockIdx.y == 0) {
+    // every counter update of the batch is done (the scan precedes this
+    // kernel): the final state is reachable, the batch's peak occupancy
+    // (all writes before the reads) is within Eq. 2, and no counter went back
+    for (uint32_t q = threadIdx.x; q < c.n_fifos; q += blockDim.x) {
+      const FifoDev &f = c.fifos[q];
+      const uint32_t wa = b.fifo_wacc[q];
+      PRUNE_DEBUG_CHECK(fifo_counters_ok(f.r, f.Q, f.C, f.writes, f.reads, f.tokens_written, f.tokens_read) &&
+                            f.max_occ <= fifo_capacity(f.r, f.Q, f.C) && f.tokens_read >= b.s_rsnap[q] &&
+                            f.writes >= b.s_base[wa],
+                        c.err);
+    }
+  }
   if (i >= c.B) return;
   const uint32_t Bc = c.Bcap, last = c.B - 1;
   {

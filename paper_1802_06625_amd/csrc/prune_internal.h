@@ -24,7 +24,23 @@ enum : uint32_t {
   kErrRate = 2u,       // rate parameter outside 1..atr
   kErrCount = 4u,      // block count differs from the firing's rate
   kErrTrace = 8u,      // trace buffer overflow
+  kErrInvariant = 16u, // a FIFO's counters broke an invariant (PRUNE_DEBUG builds)
 };
+
+// Checks of the bookkeeping kernels that only PRUNE_DEBUG builds compile:
+// a failed one sets kErrInvariant in the device error word.
+#if defined(PRUNE_DEBUG)
+#define PRUNE_DEBUG_CHECK(cond, err) \
+  do {                               \
+    if (!(cond)) atomicOr((err), ::prune::kErrInvariant); \
+  } while (0)
+constexpr bool kDebugBuild = true;
+#else
+#define PRUNE_DEBUG_CHECK(cond, err) \
+  do {                               \
+  } while (0)
+constexpr bool kDebugBuild = false;
+#endif
 
 // ---------------------------------------------------------------- device tables
 struct FifoDev {

@@ -96,4 +96,23 @@ PRUNE_HD inline bool fifo_state_ok(uint32_t r, uint32_t Q, uint32_t C, int64_t i
   return inflight >= -(int64_t)(Q / r) && occ >= 0 && (uint64_t)occ <= fifo_capacity(r, Q, C);
 }
 
+// The four counters a FIFO keeps (block accesses written and read, tokens
+// written and read) after a bookkeeping update: the block state is one the
+// blocking rules reach (fifo_state_ok), no access carries more than r
+// tokens, and the token occupancy Q + tokens written - tokens read lies in
+// [0, Eq. 2 capacity].
+PRUNE_HD inline bool fifo_counters_ok(uint32_t r, uint32_t Q, uint32_t C, uint64_t writes, uint64_t reads,
+                                      uint64_t tokens_written, uint64_t tokens_read) {
+  if (!fifo_state_ok(r, Q, C, (int64_t)writes - (int64_t)reads)) return false;
+  if (tokens_written > writes * r || tokens_read > reads * r) return false;
+  if (tokens_read > (uint64_t)Q + tokens_written) return false;
+  return (uint64_t)Q + tokens_written - tokens_read <= fifo_capacity(r, Q, C);
+}
+
+// One update of a counter pair (accesses, tokens) from (n0, t0) to (n1, t1):
+// neither goes back, and the new accesses carry at most r tokens each.
+PRUNE_HD inline bool fifo_advance_ok(uint32_t r, uint64_t n0, uint64_t t0, uint64_t n1, uint64_t t1) {
+  return n1 >= n0 && t1 >= t0 && t1 - t0 <= (n1 - n0) * r;
+}
+
 }  // namespace prune

@@ -1768,6 +1768,8 @@ prune_status prune_graph_sync(prune_graph_t g, prune_stream_t stream) {
     if (e & kErrRate) return fail(PRUNE_E_TOKEN, "rate parameter outside 1..atr");
     if (e & kErrCount) return fail(PRUNE_E_TOKEN, "block count differs from the firing's rate (or sink output full)");
     if (e & kErrTrace) return fail(PRUNE_E_CAPACITY, "trace buffer overflow");
+    if (e & kErrInvariant)
+      return fail(PRUNE_E_RULE, "bookkeeping broke a FIFO invariant (occupancy outside Eq. 2, or a counter going back)");
   }
   return PRUNE_OK;
 }
@@ -1906,6 +1908,8 @@ prune_status prune_rule_config_token(uint32_t mode, uint32_t Kmax, const prune_s
   *out = config_map(mode, Kmax, *side);
   return PRUNE_OK;
 }
+
+uint32_t prune_build_flags(void) { return kDebugBuild ? PRUNE_BUILD_DEBUG : 0u; }
 
 const char *prune_status_string(prune_status s) {
   switch (s) {

@@ -5,7 +5,9 @@ UndefinedBehaviorSanitizer (g++, no GPU) and checked against the oracle:
   matched and mismatched control streams, delays and FIFO depths;
 * the compile-time analysis (design_analysis.cpp) on seeded structures;
 * the FIFO and configuration rules the kernels use (prune_rules.h) under
-  random traffic: order, Eq. 2 occupancy, counters, buffer bounds."""
+  random traffic: order, Eq. 2 occupancy, counters, buffer bounds, and the
+  invariant checks of PRUNE_DEBUG builds on that traffic and on planted
+  mistakes."""
 import os
 import shutil
 import subprocess
@@ -56,8 +58,8 @@ def _run(exe, text):
 def test_fifo_and_config_rules(tools):
     out = _run(tools["rules_check"], "")
     assert out.startswith("ok "), out
-    cases, accesses = (int(v) for v in out.split()[1:3])
-    assert cases > 300 and accesses > 100000
+    cases, accesses, planted = (int(v) for v in out.split()[1:4])
+    assert cases > 300 and accesses > 100000 and planted > 5000
 
 
 # ---------------------------------------------------------------- stop classification
