@@ -249,8 +249,8 @@ prune_status prune_fb_forward_variant(const prune_fb_desc *desc, const void *x, 
   hipStream_t s = (hipStream_t)stream;
   launch_direct_prep(*desc, (const float2 *)x, (const float2 *)taps, (const prune_fb_frame *)frames,
                      (float2 *)y, tile, sc->desc, sc->items, sc->ctr, sc->ctr + 1, sc->ctr + 2, s);
-  // four workgroups per CU, the residency of the J = 8, 256-thread forward kernels
-  const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 4, items);
+  // the persistent grid: every workgroup slot of the chip, or one per tile
+  const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * fb_variant_resident(variant), items);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timing_on() && !g_tuning;
   if (timed) {   // events that cannot be created leave the launch untimed
@@ -310,7 +310,7 @@ prune_status prune_fb_forward_noalloc(const prune_fb_desc *desc, const void *x, 
   // forward kernel reads them; the error word is not read on this path
   launch_direct_prep(*desc, (const float2 *)x, (const float2 *)taps, (const prune_fb_frame *)frames,
                      (float2 *)y, tile, fd, it, ctr, ctr + 1, ctr + 2, s);
-  const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * 4, items);
+  const uint32_t grid = (uint32_t)std::min<size_t>((size_t)ncu() * fb_variant_resident(variant), items);
   fb_forward_launch(variant, fd, it, ctr, (unsigned int *)(ctr + 1), grid, s);
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
 }

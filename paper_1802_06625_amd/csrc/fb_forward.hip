@@ -26,6 +26,9 @@
 // taps; the tap coefficients of the chunk are LDS broadcasts.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "prune_internal.h"
 #include "runtime_kernels.h"
 
@@ -301,7 +304,18 @@ struct FbVariant {
   int tile, WG;   // outputs per work item, threads per workgroup
   void (*launch)(const FbFrameDesc *, const WorkItem *, const uint32_t *, unsigned int *,
                  uint32_t grid, hipStream_t, hipEvent_t, hipEvent_t);
+  int (*resident)();   // workgroups of the kernel resident per CU
 };
+
+template <int J, int WG, int WAVES, int G = J, bool PIPE = false>
+static int fwd_resident() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(
+                                                           &k_fb_forward<J, WG, WAVES, G, PIPE>),
+                                                   WG, 0) != hipSuccess)
+    n = 0;
+  return n;
+}
 
 // With events, the dispatch itself records the kernel's start and end
 // (hipExtLaunchKernelGGL): no marker packets, no gaps around the kernel.
@@ -321,15 +335,23 @@ static const FbVariant kVariants[] = {
     // vector Horner kernels: J outputs per lane, WG threads, waves-per-EU
     // hint, Horner chains of G outputs advanced together, next tap's
     // coefficients read ahead (p) or not (g)
-    {"valu_horner_J8_WG256_p4", 8 * 256, 256, launch_fwd<8, 256, 1, 4, true>},
-    {"valu_horner_J4_WG256_w3", 4 * 256, 256, launch_fwd<4, 256, 3>},
-    {"valu_horner_J8_WG128_w2", 8 * 128, 128, launch_fwd<8, 128, 2>},
-    {"valu_horner_J4_WG128_w4", 4 * 128, 128, launch_fwd<4, 128, 4>},
-    {"valu_horner_J8_WG256_p2", 8 * 256, 256, launch_fwd<8, 256, 1, 2, true>},
+    {"valu_horner_J8_WG256_p4", 8 * 256, 256, launch_fwd<8, 256, 1, 4, true>,
+      fwd_resident<8, 256, 1, 4, true>},
+    {"valu_horner_J4_WG256_w3", 4 * 256, 256, launch_fwd<4, 256, 3>,
+      fwd_resident<4, 256, 3>},
+    {"valu_horner_J8_WG128_w2", 8 * 128, 128, launch_fwd<8, 128, 2>,
+      fwd_resident<8, 128, 2>},
+    {"valu_horner_J4_WG128_w4", 4 * 128, 128, launch_fwd<4, 128, 4>,
+      fwd_resident<4, 128, 4>},
+    {"valu_horner_J8_WG256_p2", 8 * 256, 256, launch_fwd<8, 256, 1, 2, true>,
+      fwd_resident<8, 256, 1, 2, true>},
     // matrix-core block-Toeplitz kernels: NT result tiles per wave, NW waves
-    {"mfma_toeplitz_NT4_W4", 4 * 256 * 4, 256, launch_fb_mfma<4, 4>},
-    {"mfma_toeplitz_NT2_W4", 2 * 256 * 4, 256, launch_fb_mfma<2, 4>},
-    {"mfma_toeplitz_NT4_W2", 4 * 256 * 2, 128, launch_fb_mfma<4, 2>},
+    {"mfma_toeplitz_NT4_W4", 4 * 256 * 4, 256, launch_fb_mfma<4, 4>,
+      fb_mfma_resident<4, 4>},
+    {"mfma_toeplitz_NT2_W4", 2 * 256 * 4, 256, launch_fb_mfma<2, 4>,
+      fb_mfma_resident<2, 4>},
+    {"mfma_toeplitz_NT4_W2", 4 * 256 * 2, 128, launch_fb_mfma<4, 2>,
+      fb_mfma_resident<4, 2>},
 };
 
 int fb_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -338,6 +360,18 @@ const char *fb_variant_name(int v) {
 }
 int fb_variant_tile(int v) { return kVariants[v - 1].tile; }
 int fb_variant_wg(int v) { return kVariants[v - 1].WG; }
+
+// Queried once per variant (on the current device; every device here is
+// the same gfx950 part).
+int fb_variant_resident(int v) {
+  static std::atomic<int> cache[sizeof(kVariants) / sizeof(kVariants[0])] = {};
+  int n = cache[v - 1].load();
+  if (n <= 0) {
+    n = std::max(1, kVariants[v - 1].resident());
+    cache[v - 1].store(n);
+  }
+  return n;
+}
 
 void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,
                        const uint32_t *n_items, unsigned int *ticket, uint32_t grid,

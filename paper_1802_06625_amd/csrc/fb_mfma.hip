@@ -240,6 +240,18 @@ void launch_fb_mfma(const FbFrameDesc *f, const WorkItem *it, const uint32_t *n,
     hipLaunchKernelGGL((k_fb_mfma<NT, NW>), dim3(grid), dim3(64 * NW), 0, s, f, it, n, ticket);
 }
 
+template <int NT, int NW>
+int fb_mfma_resident() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_fb_mfma<NT, NW>),
+                                                   64 * NW, 0) != hipSuccess)
+    n = 0;
+  return n;
+}
+template int fb_mfma_resident<4, 4>();
+template int fb_mfma_resident<2, 4>();
+template int fb_mfma_resident<4, 2>();
+
 template void launch_fb_mfma<4, 4>(const FbFrameDesc *, const WorkItem *, const uint32_t *,
                                    unsigned int *, uint32_t, hipStream_t, hipEvent_t,
                                    hipEvent_t);

@@ -1461,7 +1461,7 @@ prune_status prune_graph_finalize(prune_graph_t g, uint32_t C) {
     }
   }
   g->tile = (uint32_t)fb_variant_tile(g->variant);
-  g->fb_grid = g->ncu * 4;   // residency of the J = 8, 256-thread forward kernels per CU
+  g->fb_grid = g->ncu * (uint32_t)fb_variant_resident(g->variant);   // every workgroup slot
   TRY(alloc_scratch(g));
   if (g->fast_batch) {
     HIPCHECK(hipStreamCreateWithFlags(&g->side_stream, hipStreamNonBlocking));

@@ -106,6 +106,11 @@ int fb_variant_count();
 const char *fb_variant_name(int v);
 int fb_variant_tile(int v);
 int fb_variant_wg(int v);
+// Workgroups of variant v resident per CU: the persistent grid is this many
+// per CU.
+int fb_variant_resident(int v);
+template <int NT, int NW>
+int fb_mfma_resident();
 // e0/e1 (may be null): events that receive the kernel's own start and end.
 void fb_forward_launch(int v, const FbFrameDesc *frames, const WorkItem *items,
                        const uint32_t *n_items, unsigned int *ticket, uint32_t grid,
