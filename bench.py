@@ -550,7 +550,7 @@ def bench_direct(name, steps, warmup):
     t_b = _time_events(bwd, steps, warmup)
     t_bt = _time_events(bwd_taps, steps, warmup)
     bwd_by_form = {}
-    for form in (1, 2):
+    for form in (1, 2, 3):
         ops.set_bwd_variant(form)
         try:
             bwd_by_form[ops.bwd_variant_name(form)] = round(_time_events(bwd, steps, warmup), 4)

@@ -606,8 +606,11 @@ prune_status prune_fb_tuned_variant(const prune_fb_desc *desc, int *variant);
 /* Backward form: 0 = automatic (autotuned per shape class like the forward,
  * cached per process), 1 = vector kernel (Horner form in r), 2 = matrix-core
  * kernels (block-Toeplitz grad_u and blocked grad_h, Gauss three-product
- * complex arithmetic).  Both give the same result up to fp32 rounding and
- * the same deterministic float64 reduction of grad_h. */
+ * complex arithmetic), 3 = one matrix-core kernel computing both gradients
+ * per tile as plain real products (taps of all banks folded per power, the
+ * cotangent's Hankel matrix against the taps for grad_x and against the
+ * basis planes for grad_h).  All give the same result up to fp32 rounding
+ * and the same deterministic float64 reduction of grad_h's tile partials. */
 prune_status prune_set_bwd_variant(int variant);
 const char *prune_bwd_variant_name(int variant);
 /* Run the backward autotuner now for (L, K, n) on a synthetic batch

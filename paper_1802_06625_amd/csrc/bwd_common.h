@@ -87,6 +87,38 @@ __device__ inline void red_stream_block(uint32_t E, const double2 *__restrict__ 
   __syncthreads();
 }
 
+// Samples of grad_x outside every frame get a zero gradient.  Run by every
+// workgroup of a grid after its items: workgroup k takes frames k, k + grid,
+// ... and zeroes the gap after each (up to the next frame of its stream or
+// the stream's end) and, for a stream's first frame (sfirst), the samples
+// before it; then streams without frames.  Frame samples are written by the
+// items only, so the two never touch one sample.  (Positions are clamped to
+// the stream: a frame out of range has n = 0.)
+__device__ inline void bwd_zero_gaps(const prune_fb_desc &d, const BwdFrame *__restrict__ bf,
+                                     const uint32_t *__restrict__ sfirst, float2 *__restrict__ gxs) {
+  const uint64_t N = d.stream_len;
+  const uint32_t t = threadIdx.x, nt = blockDim.x;
+  for (uint32_t f = blockIdx.x; f < d.n_frames; f += gridDim.x) {
+    const BwdFrame F = bf[f];
+    if (F.stream >= d.n_streams) continue;
+    float2 *row = gxs + (size_t)F.stream * N;
+    const uint64_t end = min((uint64_t)F.t0 + F.n, N);
+    uint64_t nxt = N;
+    if (f + 1 < d.n_frames) {
+      const BwdFrame G = bf[f + 1];
+      if (G.stream == F.stream) nxt = min((uint64_t)G.t0, N);
+    }
+    for (uint64_t q = end + t; q < nxt; q += nt) row[q] = make_float2(0.f, 0.f);
+    if (sfirst[F.stream] == f)
+      for (uint64_t q = t; q < min((uint64_t)F.t0, N); q += nt) row[q] = make_float2(0.f, 0.f);
+  }
+  for (uint32_t st = blockIdx.x; st < d.n_streams; st += gridDim.x) {
+    if (sfirst[st] != 0xffffffffu) continue;
+    float2 *row = gxs + (size_t)st * N;
+    for (uint64_t q = t; q < N; q += nt) row[q] = make_float2(0.f, 0.f);
+  }
+}
+
 // Matrix-core adjoint over the same work items (one tile of kBT samples of
 // one frame each) as the vector kernel:
 //  grad_x at the tile's inputs from the frame's own outputs, and
@@ -104,5 +136,13 @@ void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkIt
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
                         const uint32_t *n_items, unsigned int *ticket, float2 *partial,
                         uint32_t max_items, uint32_t grid, hipStream_t s);
+// Both gradients as plain matrix products in one pass over each tile
+// (fb_bwd_gemm.hip): grad_x at the tile's inputs (a null gx skips it; the
+// halo rows go to hg and the samples outside every frame are zeroed), and
+// the tile's grad_h partial row (a null partial skips it).  The grid is every
+// resident workgroup slot of ncu CUs, at most max_items workgroups.
+void launch_bwd_gemm(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
+                     const uint32_t *n_items, unsigned int *ticket, float2 *hg, float2 *partial,
+                     uint32_t max_items, uint32_t ncu, const uint32_t *sfirst, float2 *gx, hipStream_t s);
 
 }  // namespace prune

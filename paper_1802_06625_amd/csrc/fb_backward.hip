@@ -514,7 +514,9 @@ static prune_status check_bwd_desc(const prune_fb_desc *d) {
   return PRUNE_OK;
 }
 
-constexpr int kBwdVariants = 2;   // 1: vector Horner kernel, 2: matrix-core kernels
+// 1: vector Horner kernel, 2: matrix-core block-Toeplitz kernels, 3: one
+// matrix-core kernel of plain products for both gradients
+constexpr int kBwdVariants = 3;
 static std::atomic<int> g_bwd_forced{0};
 static std::mutex g_bwd_mu;
 static std::map<std::string, int> g_bwd_tuned;
@@ -562,6 +564,7 @@ const char *prune_bwd_variant_name(int variant) {
   switch (variant) {
     case 1: return "valu_horner";
     case 2: return "mfma_toeplitz";
+    case 3: return "mfma_gemm";
     default: return "auto";
   }
 }
@@ -653,21 +656,26 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
       return PRUNE_E_HIP;
     return PRUNE_OK;
   }
-  // Without grad_x only the matrix-core grad_h kernel runs (the vector
-  // kernel computes both gradients in one pass).
-  const bool mfma = variant == 2 || !gx;
+  // Without grad_x the vector form runs the block-Toeplitz grad_h kernel
+  // (the vector kernel computes both gradients in one pass).
+  const bool gemm = variant == 3;
+  const bool mfma = !gemm && (variant == 2 || !gx);
   hipLaunchKernelGGL(k_bwd_prep, dim3(1), dim3(1024), 0, s, d, (const float2 *)x, (const float2 *)taps,
                      (const prune_fb_frame *)frames, (const float2 *)gy, (float2 *)gx, bf, items, cnt,
                      sb, se, cov, sfirst);
   // grad_x starts as zero outside the frames' coverage (the matrix-core
   // grad_x kernel zeroes those samples itself)
-  if (gx && !mfma)
+  if (gx && !mfma && !gemm)
     hipLaunchKernelGGL(k_bwd_gapfill, dim3(d.n_streams, 64), dim3(256), 0, s, d, cov, (float2 *)gx);
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
-  if (mfma) {
+  if (gemm) {
+    // one dynamic work ticket (cnt[1], cleared by k_bwd_prep)
+    launch_bwd_gemm(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg, gtaps ? partial : nullptr, L.max_items,
+                    (uint32_t)ncu, sfirst, (float2 *)gx, s);
+  } else if (mfma) {
     // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids of
     // 3 and 2 workgroups per CU, the fastest measured (at their register use
     // the kernels keep 2 and 1 workgroups resident per CU)
@@ -682,7 +690,7 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
     hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
   }
   if (gx && L.H) {
-    if (!mfma)   // the matrix-core grad_x kernel computes the halo rows itself
+    if (!mfma && !gemm)   // the matrix-core grad_x kernels compute the halo rows themselves
       hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
     hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
                        bf, hg, (float2 *)gx);

@@ -247,33 +247,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
     }
     __syncthreads();   // s_g and s_h are rewritten by the next item
   }
-  // Samples outside every frame get a zero gradient: workgroup k takes frames
-  // k, k + grid, ... and zeroes the gap after each (up to the next frame of
-  // its stream or the stream's end) and, for a stream's first frame, the
-  // samples before it; then streams without frames.  Frame samples are
-  // written by the items above only, so the two never touch one sample.
-  // (Positions are clamped to the stream: a frame out of range has n = 0.)
-  if (!sfirst) return;
-  const uint64_t N = d.stream_len;
-  for (uint32_t f = blockIdx.x; f < d.n_frames; f += gridDim.x) {
-    const BwdFrame F = bf[f];
-    if (F.stream >= d.n_streams) continue;
-    float2 *row = gxs + (size_t)F.stream * N;
-    const uint64_t end = min((uint64_t)F.t0 + F.n, N);
-    uint64_t nxt = N;
-    if (f + 1 < d.n_frames) {
-      const BwdFrame G = bf[f + 1];
-      if (G.stream == F.stream) nxt = min((uint64_t)G.t0, N);
-    }
-    for (uint64_t q = end + t; q < nxt; q += kWG) row[q] = make_float2(0.f, 0.f);
-    if (sfirst[F.stream] == f)
-      for (uint64_t q = t; q < min((uint64_t)F.t0, N); q += kWG) row[q] = make_float2(0.f, 0.f);
-  }
-  for (uint32_t st = blockIdx.x; st < d.n_streams; st += gridDim.x) {
-    if (sfirst[st] != 0xffffffffu) continue;
-    float2 *row = gxs + (size_t)st * d.stream_len;
-    for (uint64_t q = t; q < d.stream_len; q += kWG) row[q] = make_float2(0.f, 0.f);
-  }
+  if (sfirst) bwd_zero_gaps(d, bf, sfirst, gxs);
 }
 
 // ------------------------------------------------------------------ grad_h

@@ -187,11 +187,11 @@ def test_variant_selection_arguments():
     assert lib.prune_set_fb_variant(n + 1) == L.E_ARG
     assert lib.prune_set_fb_variant(-1) == L.E_ARG
     assert lib.prune_set_fb_variant(0) == L.OK
-    assert [lib.prune_bwd_variant_name(v).decode() for v in (0, 1, 2)] == \
-        ["auto", "valu_horner", "mfma_toeplitz"]
-    assert lib.prune_set_bwd_variant(3) == L.E_ARG
+    assert [lib.prune_bwd_variant_name(v).decode() for v in (0, 1, 2, 3)] == \
+        ["auto", "valu_horner", "mfma_toeplitz", "mfma_gemm"]
+    assert lib.prune_set_bwd_variant(4) == L.E_ARG
     assert lib.prune_set_bwd_variant(-1) == L.E_ARG
-    for v in (2, 1, 0):
+    for v in (3, 2, 1, 0):
         assert lib.prune_set_bwd_variant(v) == L.OK
     v = C.c_int()
     assert lib.prune_autotune_bwd(0, 7, 1024, C.byref(v)) == L.E_ARG

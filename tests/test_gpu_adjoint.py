@@ -27,7 +27,7 @@ def _rows(wl):
     return [(s, t0, n, m, r) for s in range(wl.n_streams) for (t0, n, m, r) in stream_frames(wl, s)]
 
 
-BWD_FORMS = [1, 2]      # 1: vector kernel, 2: matrix-core kernels
+BWD_FORMS = [1, 2, 3]   # 1: vector kernel, 2: block-Toeplitz matrix-core kernels, 3: plain-product kernel
 
 
 def _backward(x, t, fr, gy, Kmax, bank_L, mfl, form):
@@ -41,7 +41,7 @@ def _backward(x, t, fr, gy, Kmax, bank_L, mfl, form):
 
 
 def test_bwd_variant_names():
-    assert [ops.bwd_variant_name(v) for v in (0, 1, 2)] == ["auto", "valu_horner", "mfma_toeplitz"]
+    assert [ops.bwd_variant_name(v) for v in (0, 1, 2, 3)] == ["auto", "valu_horner", "mfma_toeplitz", "mfma_gemm"]
 
 
 @pytest.mark.parametrize("form", BWD_FORMS)
@@ -246,9 +246,9 @@ def test_direct_ops_random_configurations(seed):
 @pytest.mark.parametrize("form", BWD_FORMS)
 def test_backward_optional_gradients(form):
     """A gradient that is not wanted is not computed: grad_x alone equals the
-    grad_x of the full call bit for bit; grad_taps alone comes from the
-    matrix-core grad_h kernel (equal bit for bit to the full call's in that
-    form) and matches the oracle in either form."""
+    grad_x of the full call bit for bit; grad_taps alone comes from a
+    matrix-core kernel (equal bit for bit to the full call's in the
+    matrix-core forms) and matches the oracle in every form."""
     announce(f"backward optional gradients form {form}")
     wl = synth.scaled("C4", cotangent=True)
     rows = _rows(wl)
@@ -265,7 +265,7 @@ def test_backward_optional_gradients(form):
         ops.set_bwd_variant(0)
     assert none1 is None and none2 is None
     assert torch.equal(gx_only, gx_full)
-    if form == 2:
+    if form in (2, 3):
         assert torch.equal(gt_only, gt_full)
     _, rt = fb_stream_adjoint(wl.x[0], stream_frames(wl, 0), wl.taps[0], wl.bank_L, wl.Kmax, wl.gy[0])
     assert rel_l2(gt_only.cpu().numpy()[0], rt) <= TOL
