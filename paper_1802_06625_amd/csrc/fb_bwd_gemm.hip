@@ -103,6 +103,8 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
   static_assert(kGW * LT * 4 * 64 <= kGW * kMaxP * kUPlane, "W sum fits in the basis planes");
   static_assert(PRUNE_MAX_L * kMaxP <= kGWin, "W table fits in the window");
   constexpr int NH = (LT * RT <= 2) ? 2 : 1;   // W accumulator sets (alternate steps)
+  constexpr bool ACACHE = 8 * LT * RT <= 16;   // grad_x row operand kept in registers
+  constexpr int WU = LT * RT <= 2 ? 8 : 2;       // W groups unrolled (all of them when small)
   constexpr int NGW = (kGWin + kGWG - 1) / kGWG;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j16 = lane & 15, q4 = lane >> 4;
@@ -214,6 +216,15 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
         tab_frame = wi.frame;
       }
       __syncthreads();
+      // the grad_x row operand of every step in registers, when it fits
+      float acache[ACACHE ? 8 * LT * RT : 1];
+      if constexpr (ACACHE) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int s = 0; s < 8 * LT; ++s)
+            acache[rt * 8 * LT + s] = s < Sf ? s_ax[(rt * kAxSteps + s) * 64 + lane] : 0.f;
+      }
       // the ticket read from LDS is the same in every lane: readfirstlane
       // lets the compiler keep it, and all that depends on it, in scalars
       if (it == i0) grp_next = __builtin_amdgcn_readfirstlane(s_next[par ^ 1u]);
@@ -247,101 +258,184 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
           wave_sync_lds();
           // Hankel operand offset of this lane: position m0 + j16 + q4/2 (+ l), word re|im = q4&1
           const int goff = 2 * (m0 - (n0 - kPre) + j16 + (q4 >> 1)) + (q4 & 1);
-          if (want_x) {
-            floatx4 ax[4][RT];
+          // the step's work: grad_x products (ax), the W products, and the
+          // grad_x epilogue; with both gradients wanted the W products and
+          // the epilogue sit in one basic block, so that the scheduler can
+          // issue the epilogue's vector instructions while the matrix cores
+          // run
+          floatx4 ax[4][RT];
+          float gr = 0.f, gi = 0.f;
+          auto gx_products = [&]() {
 #pragma unroll
             for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
               for (int rt = 0; rt < RT; ++rt) ax[blk][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-            for (int s = 0; s < Sf; ++s) {
-              float a[RT];
+            if constexpr (ACACHE) {
+              // row operand from registers (loaded once per tile), column
+              // operands of step s + 1 read while step s is on the matrix cores
+              float bn[4];
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt) a[rt] = s_ax[(rt * kAxSteps + s) * 64 + lane];
-              float b[4];
+              for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk];
 #pragma unroll
-              for (int blk = 0; blk < 4; ++blk) b[blk] = sg[goff + 32 * blk + 4 * s];
+              for (int s = 0; s < 8 * LT; ++s) {
+                if (s < Sf) {
+                  float b[4];
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt)
+                  for (int blk = 0; blk < 4; ++blk) b[blk] = bn[blk];
+                  if (s + 1 < Sf) {
 #pragma unroll
-                for (int blk = 0; blk < 4; ++blk) ax[blk][rt] = mfma4(a[rt], b[blk], ax[blk][rt]);
-            }
-            // lane (q4, j16) holds G_p at position m0 + 16 blk + j16 for
-            // p = 8 rt + 2 q4 + e/2, re|im = e&1: its share of
-            // S1 = sum_p (p/2+1) r^p G_p and S2 = sum_p (p/2) r^p conj(G_p)
-            auto share = [&](int blk, float (&P)[4]) {
-              const float r = sr[16 * blk + j16], r2 = r * r, r4 = r2 * r2;
-              const float pw0 = ((q4 & 1) ? r2 : 1.f) * ((q4 & 2) ? r4 : 1.f);   // r^(2 q4)
-              P[0] = P[1] = P[2] = P[3] = 0.f;
+                    for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk + 4 * (s + 1)];
+                  }
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt) {
-                float pw = rt ? pw0 * (r4 * r4) : pw0;
+                  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int e2 = 0; e2 < 2; ++e2) {
-                  const float al = c_al[rt][e2] * pw, be = c_be[rt][e2] * pw;
-                  const float gr = ax[blk][rt][2 * e2], gi = ax[blk][rt][2 * e2 + 1];
-                  P[0] = fmaf(al, gr, P[0]);
-                  P[1] = fmaf(al, gi, P[1]);
-                  P[2] = fmaf(be, gr, P[2]);
-                  P[3] = fmaf(-be, gi, P[3]);
-                  pw *= r;
+                    for (int blk = 0; blk < 4; ++blk)
+                      ax[blk][rt] = mfma4(acache[rt * 8 * LT + s], b[blk], ax[blk][rt]);
                 }
               }
-            };
-            // sum over the four lane groups, leaving block q4 in lane group
-            // q4: blocks i and 2+i across lanes 32 apart, then one block of
-            // the pair across lanes 16 apart
-            const bool hi2 = q4 & 2, hi1 = q4 & 1;
-            float Q[2][4], S[4];
+            } else {
+              // operands of step s + 1 are read while step s is on the matrix
+              // cores (the index is clamped at the last step)
+              float an[RT], bn[4];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              float Pa[4], Pb[4];
-              share(i, Pa);
-              share(2 + i, Pb);
+              for (int rt = 0; rt < RT; ++rt) an[rt] = s_ax[rt * kAxSteps * 64 + lane];
+#pragma unroll
+              for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk];
+              for (int s = 0; s < Sf; ++s) {
+                float a[RT], b[4];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) a[rt] = an[rt];
+#pragma unroll
+                for (int blk = 0; blk < 4; ++blk) b[blk] = bn[blk];
+                const int s1 = min(s + 1, Sf - 1);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) an[rt] = s_ax[(rt * kAxSteps + s1) * 64 + lane];
+#pragma unroll
+                for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk + 4 * s1];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                  for (int blk = 0; blk < 4; ++blk) ax[blk][rt] = mfma4(a[rt], b[blk], ax[blk][rt]);
+              }
+            }
+          };
+          // the grad_x epilogue in six pieces: lane (q4, j16) holds G_p at
+          // position m0 + 16 blk + j16 for p = 8 rt + 2 q4 + e/2, re|im =
+          // e&1; its shares of S1 = sum_p (p/2+1) r^p G_p and
+          // S2 = sum_p (p/2) r^p conj(G_p) are summed over the four lane
+          // groups so that lane group q4 keeps block q4 (blocks i and 2+i
+          // across lanes 32 apart, then one block of the pair across lanes
+          // 16 apart), and grad_x = S1 + (x^2/r^2) S2 at position m0 + lane
+          float Pa[4], Pb[4], Q[2][4], S[4];
+          auto share = [&](int blk, float (&P)[4]) {
+            const float r = sr[16 * blk + j16], r2 = r * r, r4 = r2 * r2;
+            const float pw0 = ((q4 & 1) ? r2 : 1.f) * ((q4 & 2) ? r4 : 1.f);   // r^(2 q4)
+            P[0] = P[1] = P[2] = P[3] = 0.f;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+              float pw = rt ? pw0 * (r4 * r4) : pw0;
+#pragma unroll
+              for (int e2 = 0; e2 < 2; ++e2) {
+                const float al = c_al[rt][e2] * pw, be = c_be[rt][e2] * pw;
+                const float g_r = ax[blk][rt][2 * e2], g_i = ax[blk][rt][2 * e2 + 1];
+                P[0] = fmaf(al, g_r, P[0]);
+                P[1] = fmaf(al, g_i, P[1]);
+                P[2] = fmaf(be, g_r, P[2]);
+                P[3] = fmaf(-be, g_i, P[3]);
+                pw *= r;
+              }
+            }
+          };
+          const bool hi2 = q4 & 2, hi1 = q4 & 1;
+          auto epi_piece = [&](int k) {
+            if (k == 0 || k == 2) {
+              share(k >> 1, Pa);
+            } else if (k == 1 || k == 3) {
+              share(2 + (k >> 1), Pb);
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
                 const float mine = hi2 ? Pb[v] : Pa[v], oth = hi2 ? Pa[v] : Pb[v];
-                Q[i][v] = mine + __shfl_xor(oth, 32, 64);
+                Q[k >> 1][v] = mine + __shfl_xor(oth, 32, 64);
+              }
+            } else if (k == 4) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const float mine = hi1 ? Q[1][v] : Q[0][v], oth = hi1 ? Q[0][v] : Q[1][v];
+                S[v] = mine + __shfl_xor(oth, 16, 64);
+              }
+            } else if (k == 5) {
+              // (x^2/r^2 is taken as zero at r = 0, where S2 is zero); no
+              // contraction, so that every code path rounds the same way
+#pragma clang fp contract(off)
+              const float r2 = xv.x * xv.x + xv.y * xv.y;
+              const float inv = r2 > 0.f ? 1.f / r2 : 0.f;
+              const float er = (xv.x * xv.x - xv.y * xv.y) * inv, ei = 2.f * xv.x * xv.y * inv;
+              gr = S[0] + (er * S[2] - ei * S[3]);
+              gi = S[1] + (er * S[3] + ei * S[2]);
+            }
+          };
+          auto gx_epilogue = [&]() {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) epi_piece(k);
+          };
+          // hook(g) runs between the reads of group g+1 and the products of group g
+          auto w_products = [&](auto hook) {
+            // W over the 64 positions: rows l = 16 lt + j16, 32 steps of
+            // (two positions, re|im); alternate accumulator sets when few.
+            // Rows past the frame's taps and columns of powers beyond its
+            // highest active one (stale planes) are computed and never written.
+            // operands of four steps at a time, the next four read while
+            // the current ones are on the matrix cores
+            float ab[2][4][LT], bb[2][4][RT];
+            auto load4 = [&](int buf, int s0) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                for (int lt = 0; lt < LT; ++lt) ab[buf][k][lt] = sg[goff + 32 * lt + 4 * (s0 + k)];
+#pragma unroll
+                for (int ct = 0; ct < RT; ++ct) bb[buf][k][ct] = su[uoff[ct] + 4 * (s0 + k)];
+              }
+            };
+            load4(0, 0);
+#pragma unroll WU
+            for (int g = 0; g < 8; ++g) {
+              const int cur = g & 1;
+              if (g < 7) load4(cur ^ 1, 4 * g + 4);
+              hook(g);
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int h = NH == 2 ? (k & 1) : 0;
+#pragma unroll
+                for (int lt = 0; lt < LT; ++lt)
+#pragma unroll
+                  for (int ct = 0; ct < RT; ++ct)
+                    acc_h[h][lt][ct] = mfma4(ab[cur][k][lt], usgn[ct] * bb[cur][k][ct], acc_h[h][lt][ct]);
               }
             }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float mine = hi1 ? Q[1][v] : Q[0][v], oth = hi1 ? Q[0][v] : Q[1][v];
-              S[v] = mine + __shfl_xor(oth, 16, 64);
+          };
+          if (want_x && want_h) {
+            gx_products();
+            if constexpr (LT * RT <= 2) {
+              // W groups fully unrolled: the epilogue's pieces go between them
+              w_products([&](int g) {
+                if (g < 6) epi_piece(g);
+              });
+            } else {
+              w_products([](int) {});
+              gx_epilogue();
             }
-            // this lane's position m0 + lane: grad_x = S1 + (x^2/r^2) S2
-            float gr = S[0], gi = S[1];
-            const float r2 = xv.x * xv.x + xv.y * xv.y;
-            if (r2 > 0.f) {
-              const float inv = 1.f / r2;
-              const float er = (xv.x * xv.x - xv.y * xv.y) * inv, ei = 2.f * xv.x * xv.y * inv;
-              gr += er * S[2] - ei * S[3];
-              gi += er * S[3] + ei * S[2];
-            }
+          } else if (want_x) {
+            gx_products();
+            gx_epilogue();
+          } else {
+            w_products([](int) {});
+          }
+          if (want_x) {
             const int m = m0 + lane;
             if (ci == 0) {
               if (m >= -H) hg[(size_t)wi.frame * H + (m + H)] = make_float2(gr, gi);
             } else if (m < n) {
               F.gx[m] = make_float2(gr, gi);
-            }
-          }
-          if (want_h) {
-            // W over the 64 positions: rows l = 16 lt + j16, 32 steps of
-            // (two positions, re|im); alternate accumulator sets when few.
-            // Rows past the frame's taps and columns of powers beyond its
-            // highest active one (stale planes) are computed and never written.
-#pragma unroll 4
-            for (int s = 0; s < 32; ++s) {
-              float a[LT], b[RT];
-#pragma unroll
-              for (int lt = 0; lt < LT; ++lt) a[lt] = sg[goff + 32 * lt + 4 * s];
-#pragma unroll
-              for (int ct = 0; ct < RT; ++ct) b[ct] = usgn[ct] * su[uoff[ct] + 4 * s];
-              const int h = NH == 2 ? (s & 1) : 0;
-#pragma unroll
-              for (int lt = 0; lt < LT; ++lt)
-#pragma unroll
-                for (int ct = 0; ct < RT; ++ct) acc_h[h][lt][ct] = mfma4(a[lt], b[ct], acc_h[h][lt][ct]);
             }
           }
           wave_sync_lds();   // the planes are rewritten by the next step
