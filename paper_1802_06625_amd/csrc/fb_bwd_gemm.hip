@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
   static_assert(PRUNE_MAX_L * kMaxP <= kGWin, "W table fits in the window");
   constexpr int NH = (LT * RT <= 2) ? 2 : 1;   // W accumulator sets (alternate steps)
   constexpr bool ACACHE = 8 * LT * RT <= 16;   // grad_x row operand kept in registers
-  constexpr int WU = LT * RT <= 2 ? 8 : 2;       // W groups unrolled (all of them when small)
+  constexpr int WU = LT * RT <= 2 ? 4 : 1;       // W group pairs unrolled (all of them when small)
   constexpr int NGW = (kGWin + kGWG - 1) / kGWG;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j16 = lane & 15, q4 = lane >> 4;
@@ -286,6 +286,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
 #pragma unroll
                     for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk + 4 * (s + 1)];
                   }
+                  __builtin_amdgcn_sched_barrier(0);   // the next step's reads go first
 #pragma unroll
                   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -294,28 +295,33 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
                 }
               }
             } else {
-              // operands of step s + 1 are read while step s is on the matrix
-              // cores (the index is clamped at the last step)
-              float an[RT], bn[4];
+              // steps in pairs, each operand buffer keeping its role: the
+              // reads of step s + 1 are issued before the products of step s
+              // (the step index is clamped at the last step)
+              float an[2][RT], bn[2][4];
+              auto load1 = [&](int buf, int st) {
+                st = min(st, Sf - 1);
 #pragma unroll
-              for (int rt = 0; rt < RT; ++rt) an[rt] = s_ax[rt * kAxSteps * 64 + lane];
+                for (int rt = 0; rt < RT; ++rt) an[buf][rt] = s_ax[(rt * kAxSteps + st) * 64 + lane];
 #pragma unroll
-              for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk];
-              for (int s = 0; s < Sf; ++s) {
-                float a[RT], b[4];
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) a[rt] = an[rt];
-#pragma unroll
-                for (int blk = 0; blk < 4; ++blk) b[blk] = bn[blk];
-                const int s1 = min(s + 1, Sf - 1);
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) an[rt] = s_ax[(rt * kAxSteps + s1) * 64 + lane];
-#pragma unroll
-                for (int blk = 0; blk < 4; ++blk) bn[blk] = sg[goff + 32 * blk + 4 * s1];
+                for (int blk = 0; blk < 4; ++blk) bn[buf][blk] = sg[goff + 32 * blk + 4 * st];
+              };
+              auto products1 = [&](int buf) {
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                  for (int blk = 0; blk < 4; ++blk) ax[blk][rt] = mfma4(a[rt], b[blk], ax[blk][rt]);
+                  for (int blk = 0; blk < 4; ++blk) ax[blk][rt] = mfma4(an[buf][rt], bn[buf][blk], ax[blk][rt]);
+              };
+              load1(0, 0);
+              for (int st = 0; st < Sf; st += 2) {
+                load1(1, st + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                products1(0);
+                if (st + 1 < Sf) {
+                  load1(0, st + 2);
+                  __builtin_amdgcn_sched_barrier(0);
+                  products1(1);
+                }
               }
             }
           };
@@ -396,12 +402,10 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
                 for (int ct = 0; ct < RT; ++ct) bb[buf][k][ct] = su[uoff[ct] + 4 * (s0 + k)];
               }
             };
-            load4(0, 0);
-#pragma unroll WU
-            for (int g = 0; g < 8; ++g) {
-              const int cur = g & 1;
-              if (g < 7) load4(cur ^ 1, 4 * g + 4);
-              hook(g);
+            // groups in pairs, so that each buffer keeps its role (no copies
+            // between them): the reads of group g+1 are issued before the
+            // products of group g
+            auto products4 = [&](int buf) {
 #pragma unroll
               for (int k = 0; k < 4; ++k) {
                 const int h = NH == 2 ? (k & 1) : 0;
@@ -409,8 +413,20 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
                 for (int lt = 0; lt < LT; ++lt)
 #pragma unroll
                   for (int ct = 0; ct < RT; ++ct)
-                    acc_h[h][lt][ct] = mfma4(ab[cur][k][lt], usgn[ct] * bb[cur][k][ct], acc_h[h][lt][ct]);
+                    acc_h[h][lt][ct] = mfma4(ab[buf][k][lt], usgn[ct] * bb[buf][k][ct], acc_h[h][lt][ct]);
               }
+            };
+            load4(0, 0);
+#pragma unroll WU
+            for (int g = 0; g < 8; g += 2) {
+              load4(1, 4 * g + 4);
+              __builtin_amdgcn_sched_barrier(0);
+              hook(g);
+              products4(0);
+              if (g + 2 < 8) load4(0, 4 * g + 8);
+              __builtin_amdgcn_sched_barrier(0);
+              hook(g + 1);
+              products4(1);
             }
           };
           if (want_x && want_h) {
