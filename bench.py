@@ -34,9 +34,9 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
-    # The forward kernel runs up to a third slower over its first couple of dozen
-    # full-size launches on a freshly started process (measured: about 0.97 ms
-    # falling to a steady 0.72-0.74 ms on the 4096-frame batch), so the default
+    # A freshly started process runs its first couple of dozen full-size
+    # forward launches slower: the kernel's cycle count stays the same while
+    # the shader clock climbs (per-dispatch GRBM_GUI_ACTIVE), so the default
     # warm-up covers that ramp before either launch mode is timed.
     p.add_argument("--warmup", type=int, default=30)
     p.add_argument("--frames", type=int, default=0, help="override frames per batch (parity/debug)")
@@ -439,8 +439,9 @@ def _time_events(fn, steps, warmup):
 
 def _time_modes(fire_graph, fire_stream, steps, warmup, on_stream=None, with_wall=False):
     """Milliseconds per step of the two batched launch modes: both warmed up
-    first, then timed in alternating blocks (graph, stream, graph, stream),
-    so that neither mode lands in the other's warm-up.  on_stream(True/False)
+    first, then timed in blocks ordered graph, stream, stream, graph, so that
+    neither mode lands in the other's warm-up and a clock that still drifts
+    during the timed region weighs on both modes alike.  on_stream(True/False)
     brackets every stream-mode block (kernel timing).  with_wall: also the
     host wall-clock milliseconds per step of each mode, each block bracketed
     by device synchronisations."""
@@ -454,8 +455,9 @@ def _time_modes(fire_graph, fire_stream, steps, warmup, on_stream=None, with_wal
     sizes = [steps // nb + (1 if b < steps % nb else 0) for b in range(nb)]
     tot = {"graph": 0.0, "stream": 0.0}
     wall = {"graph": 0.0, "stream": 0.0}
-    for k in sizes:
-        for name, fn in (("graph", fire_graph), ("stream", fire_stream)):
+    for b, k in enumerate(sizes):
+        order = (("graph", fire_graph), ("stream", fire_stream))
+        for name, fn in (order if b % 2 == 0 else order[::-1]):
             if name == "stream" and on_stream:
                 on_stream(True)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
