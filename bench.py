@@ -51,6 +51,9 @@ def parse():
                    help="only copy a 1 GiB buffer twice (HBM counter calibration)")
     p.add_argument("--profile-only", action="store_true",
                    help="only the timed batched steps (for profiler runs)")
+    p.add_argument("--fb-variant", default="",
+                   help="force this forward kernel variant by name instead of autotuning (profiler runs "
+                        "that must see the same kernel in every counter pass)")
     return p.parse_args()
 
 
@@ -176,6 +179,8 @@ def main():
     from paper_1802_06625_amd.graph import PlainGraph
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.fb_variant:
+        ops.set_variant(ops.variant_names().index(args.fb_variant) + 1)
     if args.only:
         fn = {"c1": lambda: bench_c1(args.steps, args.warmup),
               "perframe": lambda: bench_per_frame("C2"),
