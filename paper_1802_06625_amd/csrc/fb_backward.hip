@@ -20,7 +20,9 @@
 //  k_bwd_halo   per frame: gradient of the Lmax-1 past samples its window
 //               reads (contributions that belong to earlier frames);
 //  k_bwd_fix    adds those halo gradients into the earlier frames' grad_x
-//               (each element written by exactly one thread);
+//               (each element written by exactly one thread); when the tap
+//               gradient is wanted too, the same work runs in the first
+//               workgroups of k_bwd_reduce1;
 //  k_bwd_reduce1/2  fixed-order float64 sums of the tile partials per stream.
 #include <hip/hip_runtime.h>
 
@@ -427,11 +429,9 @@ __global__ __launch_bounds__(64) void k_bwd_halo(prune_fb_desc d, const BwdFrame
 // the halo gradients of every frame whose window covers q.  Samples inside an
 // earlier frame already hold that frame's own contribution; samples in a gap
 // between frames hold zero.  Each sample is written by one thread, no atomics.
-__global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_frame *__restrict__ fr,
-                                                const BwdFrame *__restrict__ bf,
-                                                const float2 *__restrict__ hg, float2 *__restrict__ gx) {
-  const uint32_t f = blockIdx.x;
-  if (f >= d.n_frames) return;
+__device__ void bwd_fix_frame(const prune_fb_desc &d, const prune_fb_frame *__restrict__ fr,
+                              const BwdFrame *__restrict__ bf, const float2 *__restrict__ hg,
+                              float2 *__restrict__ gx, uint32_t f) {
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const int H = (int)Lmax - 1;
@@ -454,17 +454,34 @@ __global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_
   out = make_float2(out.x + acc.x, out.y + acc.y);
 }
 
+__global__ __launch_bounds__(64) void k_bwd_fix(prune_fb_desc d, const prune_fb_frame *__restrict__ fr,
+                                                const BwdFrame *__restrict__ bf,
+                                                const float2 *__restrict__ hg, float2 *__restrict__ gx) {
+  if (blockIdx.x < d.n_frames) bwd_fix_frame(d, fr, bf, hg, gx, blockIdx.x);
+}
+
 // The two reduction stages (bwd_common.h) as kernels: workgroup (stream,
 // entry block, chunk) and (stream, entry block).
+// Stage 1, one workgroup per (chunk, entry block, stream) in that order
+// along x; the first n_fix workgroups do the halo fix-up of frames 0 ..
+// n_fix-1 instead (they write grad_x, stage 1 reads the tile partials).
 __global__ __launch_bounds__(256) void k_bwd_reduce1(prune_fb_desc d, const float2 *__restrict__ partial,
                                                      const uint32_t *__restrict__ s_begin,
                                                      const uint32_t *__restrict__ s_end,
-                                                     double2 *__restrict__ part2) {
+                                                     double2 *__restrict__ part2, uint32_t eblocks,
+                                                     uint32_t n_fix, const prune_fb_frame *__restrict__ fr,
+                                                     const BwdFrame *__restrict__ bf,
+                                                     const float2 *__restrict__ hg, float2 *__restrict__ gx) {
   __shared__ double2 red[kRedQ][64];
+  if (blockIdx.x < n_fix) {
+    bwd_fix_frame(d, fr, bf, hg, gx, blockIdx.x);
+    return;
+  }
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
-  const uint32_t E = d.n_banks * d.Kmax * Lmax, s = blockIdx.x;
-  red_chunk_block(E, partial, s_begin[s], s_end[s], s, blockIdx.z, blockIdx.y, part2, red);
+  const uint32_t E = d.n_banks * d.Kmax * Lmax;
+  const uint32_t r = blockIdx.x - n_fix, c = r % kRedG, se = r / kRedG, s = se / eblocks, eb = se - s * eblocks;
+  red_chunk_block(E, partial, s_begin[s], s_end[s], s, c, eb, part2, red);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const double2 *__restrict__ part2,
@@ -689,16 +706,19 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   } else {
     hipLaunchKernelGGL(k_bwd_main, dim3(grid), dim3(kBWG), 0, s, d, bf, items, cnt, partial);
   }
-  if (gx && L.H) {
-    if (!mfma && !gemm)   // the matrix-core grad_x kernels compute the halo rows themselves
-      hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
-    hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
-                       bf, hg, (float2 *)gx);
+  if (gx && L.H && !mfma && !gemm)   // the matrix-core grad_x kernels compute the halo rows themselves
+    hipLaunchKernelGGL(k_bwd_halo, dim3(d.n_frames), dim3(64), 0, s, d, bf, hg);
+  // the halo fix-up rides in front of the first reduction stage when both run
+  const uint32_t n_fix = (gx && L.H) ? d.n_frames : 0u;
+  if (!gtaps) {
+    if (n_fix)
+      hipLaunchKernelGGL(k_bwd_fix, dim3(d.n_frames), dim3(64), 0, s, d, (const prune_fb_frame *)frames,
+                         bf, hg, (float2 *)gx);
+    return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
   }
-  if (!gtaps) return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
   const uint32_t eblocks = (L.E + 63) / 64;
-  hipLaunchKernelGGL(k_bwd_reduce1, dim3(d.n_streams, eblocks, kRedG), dim3(256), 0, s, d, partial, sb,
-                     se, part2);
+  hipLaunchKernelGGL(k_bwd_reduce1, dim3(n_fix + d.n_streams * eblocks * kRedG), dim3(256), 0, s, d, partial,
+                     sb, se, part2, eblocks, n_fix, (const prune_fb_frame *)frames, bf, hg, (float2 *)gx);
   hipLaunchKernelGGL(k_bwd_reduce2, dim3(d.n_streams, eblocks), dim3(256), 0, s, d, part2,
                      (float2 *)gtaps);
   return hipGetLastError() == hipSuccess ? PRUNE_OK : PRUNE_E_HIP;
