@@ -57,7 +57,8 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
                                                    const float2 *g, float2 *gx, BwdFrame *bf,
                                                    WorkItem *items, uint32_t *n_items,
                                                    uint32_t *s_begin, uint32_t *s_end,
-                                                   unsigned long long *cov, uint32_t *sfirst) {
+                                                   unsigned long long *cov, uint32_t *sfirst,
+                                                   uint32_t tile) {
   __shared__ uint32_t sm[32];
   __shared__ uint32_t s_carry;
   __shared__ uint32_t s_pre[1024], s_tl[1024];
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(1024) void k_bwd_prep(prune_fb_desc d, const float2
       b.n = ok ? q.n : 0; b.mask = q.mask; b.route = q.route; b.t0 = q.t0; b.stream = q.stream;
       b.pad0 = b.pad1 = b.pad2 = 0;
       bf[f] = b;
-      tiles = (b.n + kBT - 1) / kBT;
+      tiles = (b.n + tile - 1) / tile;
       if (b.n) {   // samples covered
         if (lds_cov) atomicAdd(&s_cov[q.stream], (unsigned long long)b.n);
         else atomicAdd(&cov[q.stream], (unsigned long long)b.n);
@@ -495,7 +496,9 @@ __global__ __launch_bounds__(256) void k_bwd_reduce2(prune_fb_desc d, const doub
 
 struct BwdLayout {
   size_t frames, items, partial, part2, hg, sbeg, send, cov, sfirst, cnt, total;
-  uint32_t max_items, E, H;
+  // work items at most: in kBT tiles, and in the plain-product form's tiles
+  // (the item list and the partial rows are sized for the larger count)
+  uint32_t max_items, max_items_gemm, E, H;
 };
 
 static BwdLayout bwd_layout(const prune_fb_desc &d) {
@@ -504,13 +507,18 @@ static BwdLayout bwd_layout(const prune_fb_desc &d) {
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = std::max(Lmax, d.L[b]);
   L.E = d.n_banks * d.Kmax * Lmax;
   L.H = Lmax - 1;
-  const size_t per = ((size_t)d.max_frame_len + kBT - 1) / kBT;
-  L.max_items = (uint32_t)std::max<size_t>(1, (size_t)d.n_frames * std::max<size_t>(per, 1));
+  auto count = [&](uint32_t tile) {
+    const size_t per = ((size_t)d.max_frame_len + tile - 1) / tile;
+    return (uint32_t)std::max<size_t>(1, (size_t)d.n_frames * std::max<size_t>(per, 1));
+  };
+  L.max_items = count(kBT);
+  L.max_items_gemm = count(bwd_gemm_tile(d));
+  const uint32_t rows = std::max(L.max_items, L.max_items_gemm);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t o = 0;
   L.frames = o; o = al(o + (size_t)d.n_frames * sizeof(BwdFrame));
-  L.items = o; o = al(o + (size_t)L.max_items * sizeof(WorkItem));
-  L.partial = o; o = al(o + (size_t)L.max_items * L.E * sizeof(float2));
+  L.items = o; o = al(o + (size_t)rows * sizeof(WorkItem));
+  L.partial = o; o = al(o + (size_t)rows * L.E * sizeof(float2));
   L.part2 = o; o = al(o + (size_t)d.n_streams * kRedG * L.E * sizeof(double2));
   L.hg = o; o = al(o + (size_t)d.n_frames * std::max<uint32_t>(L.H, 1) * sizeof(float2));
   L.sbeg = o; o = al(o + (size_t)d.n_streams * sizeof(uint32_t));
@@ -679,7 +687,7 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   const bool mfma = !gemm && (variant == 2 || !gx);
   hipLaunchKernelGGL(k_bwd_prep, dim3(1), dim3(1024), 0, s, d, (const float2 *)x, (const float2 *)taps,
                      (const prune_fb_frame *)frames, (const float2 *)gy, (float2 *)gx, bf, items, cnt,
-                     sb, se, cov, sfirst);
+                     sb, se, cov, sfirst, gemm ? bwd_gemm_tile(d) : (uint32_t)kBT);
   // grad_x starts as zero outside the frames' coverage (the matrix-core
   // grad_x kernel zeroes those samples itself)
   if (gx && !mfma && !gemm)
@@ -690,7 +698,7 @@ static prune_status fb_backward_variant(const prune_fb_desc *desc, const void *x
   const uint32_t grid = std::min<uint32_t>(L.max_items, (uint32_t)ncu * 2);
   if (gemm) {
     // one dynamic work ticket (cnt[1], cleared by k_bwd_prep)
-    launch_bwd_gemm(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg, gtaps ? partial : nullptr, L.max_items,
+    launch_bwd_gemm(d, bf, items, cnt, (unsigned int *)(cnt + 1), hg, gtaps ? partial : nullptr, L.max_items_gemm,
                     (uint32_t)ncu, sfirst, (float2 *)gx, s);
   } else if (mfma) {
     // dynamic work tickets (cnt[1], cnt[2], cleared by k_bwd_prep); grids of

@@ -56,6 +56,14 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// A sample read as a global-memory load: pointers taken from the frame
+// descriptors are generic, and generic (flat) loads also count against the
+// LDS wait counter, so that every wait for an LDS read would wait for them.
+__device__ __forceinline__ float2 ld_global(const float2 *p) {
+  typedef __attribute__((address_space(1))) const unsigned long long gword;
+  return __builtin_bit_cast(float2, *(const gword *)(const unsigned long long *)p);
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
     return (c == 0 && (tile != 0 || H == 0)) ? kGW : c;
   };
   auto x_at = [&](const BwdFrame &F, int m) {   // inputs of the frame or the stream's history
-    return (!F.route && m < (int)F.n && m >= -(int)F.t0) ? F.x[m] : make_float2(0.f, 0.f);
+    return (!F.route && m < (int)F.n && m >= -(int)F.t0) ? ld_global(F.x + m) : make_float2(0.f, 0.f);
   };
 
   // a tile's cotangent window and this wave's first input sample, loaded
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
 #pragma unroll
     for (int i = 0; i < NGW; ++i) {
       const int k = t + i * kGWG, p = base + k;
-      gv[i] = (k < kGWin && p >= 0 && p < n) ? F.g[p] : make_float2(0.f, 0.f);
+      gv[i] = (k < kGWin && p >= 0 && p < n) ? ld_global(F.g + p) : make_float2(0.f, 0.f);
     }
     xn = x_at(F, base + 64 * first_ci(wi.tile) + lane);
   };
@@ -205,7 +213,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
           if (p < (int)d.Kmax) {
             for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
               if (((F.mask >> (bank * d.Kmax + p)) & 1u) && l < (int)d.L[bank]) {
-                const float2 h = F.taps[((size_t)bank * d.Kmax + p) * Lmax + l];
+                const float2 h = ld_global(F.taps + ((size_t)bank * d.Kmax + p) * Lmax + l);
                 a += h.x;
                 b += h.y;
               }
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
         // passthrough-routed frame: grad_x = g over the tile, no tap gradient
         if (want_x)
           for (int k = t; k < kBT; k += kGWG)
-            if (n0 + k < n) F.gx[n0 + k] = F.g[n0 + k];
+            if (n0 + k < n) F.gx[n0 + k] = ld_global(F.g + n0 + k);
       } else {
         float2 xv = x_first;
         for (int ci = first_ci(wi.tile); ci < kChunks; ci += kGW) {
@@ -510,6 +518,263 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
   if (want_x && sfirst) bwd_zero_gaps(d, bf, sfirst, gxs);
 }
 
+// One-wave form for small shapes (at most 8 powers, at most 16 taps): the
+// same products, with every wave on its own work and no workgroup barriers,
+// so that waves drift out of phase and one wave's loads overlap another's
+// products.  Items are tiles of kWaveT positions (the preparation kernel's
+// tile for this form); a frame's first tile also takes the 64 history
+// positions.  Per 64-position step the wave stages the cotangent window
+// (positions m0 .. m0+127) and the basis planes in its own LDS, the next
+// step's inputs and window are read into registers meanwhile, and W is kept
+// over a run of consecutive tiles of one frame (the run's first row holds
+// it, the others are zero).  The grad_x row operand (the folded taps) lives
+// in registers, rebuilt when the frame changes.  Work is assigned
+// statically: with every wave resident and tiles of equal cost, a shared
+// atomic ticket per group only adds its round trip (measured at twice the
+// kernel time on 256 frames of 8192 samples).
+constexpr int kWaveT = 512;
+constexpr int kWWin = 128;   // cotangent window positions per step
+
+// NS: grad_x contraction steps (two taps each) taken for every frame: 4 when
+// no bank has more than 8 taps, else 8 (the tap table is zero past a frame's
+// own taps, so that the extra steps add zeros).
+template <int NS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_bwd_gemm_wave(
+    prune_fb_desc d, const BwdFrame *__restrict__ bf, const WorkItem *__restrict__ items,
+    const uint32_t *__restrict__ n_items, float2 *__restrict__ hg, float2 *__restrict__ partial, uint32_t run,
+    const uint32_t *__restrict__ sfirst, float2 *__restrict__ gxs) {
+  __shared__ float2 s_gw[kWWin];
+  __shared__ float s_pl[8 * kUPlane];
+  __shared__ float s_rw[64];
+  const int lane = threadIdx.x, j16 = lane & 15, q4 = lane >> 4;
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
+  const int H = (int)Lmax - 1;
+  const uint32_t E = d.n_banks * d.Kmax * Lmax;
+  const uint32_t ni = *n_items;
+  const uint32_t R = min(max(run, 1u), 8u), ng = (ni + R - 1) / R;
+  const bool want_x = gxs != nullptr, want_h = partial != nullptr;
+  const float *const sg = reinterpret_cast<const float *>(s_gw);
+  float c_al[2], c_be[2];
+#pragma unroll
+  for (int e2 = 0; e2 < 2; ++e2) {
+    c_be[e2] = 0.5f * (float)(2 * q4 + e2);
+    c_al[e2] = c_be[e2] + 1.f;
+  }
+  const int p_col = j16 >> 1, c_col = j16 & 1, cp = q4 & 1;
+  const int uoff = p_col * kUPlane + 2 * (q4 >> 1) + (cp ^ c_col);
+  const float usgn = (c_col && !cp) ? -1.f : 1.f;
+  // the Hankel operand offset of this lane within the window (position
+  // j16 + q4/2, word re|im = q4&1)
+  const int goff = 2 * (j16 + (q4 >> 1)) + (q4 & 1);
+  auto x_at = [&](const BwdFrame &F, int m) {
+    return (!F.route && m < (int)F.n && m >= -(int)F.t0) ? ld_global(F.x + m) : make_float2(0.f, 0.f);
+  };
+  auto g_at = [&](const BwdFrame &F, int m) {
+    return (!F.route && m >= 0 && m < (int)F.n) ? ld_global(F.g + m) : make_float2(0.f, 0.f);
+  };
+  float acache[8];
+  uint32_t tab_frame = 0xffffffffu;
+  // static assignment, one contiguous range of groups per XCD (workgroups
+  // are dealt to the 8 XCDs round robin), so that neighbouring tiles, which
+  // share cotangent samples, are read through one L2
+  const uint32_t nx = (gridDim.x % 8u) ? 1u : 8u, per_x = gridDim.x / nx;
+  const uint32_t chunk = (ng + nx - 1) / nx, xcd = blockIdx.x % nx;
+  const uint32_t g_end = min(ng, (xcd + 1) * chunk);
+  for (uint32_t grp = xcd * chunk + blockIdx.x / nx; grp < g_end; grp += per_x) {
+    const uint32_t i0 = grp * R, i1 = min(ni, i0 + R);
+    floatx4 acc_h[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+    uint32_t seg0 = i0;
+    for (uint32_t it = i0; it < i1; ++it) {
+      const WorkItem wi = items[it];
+      const BwdFrame F = bf[wi.frame];
+      const int n = (int)F.n, n0 = (int)wi.tile * kWaveT;
+      const FrameShape fs = F.route ? FrameShape{0, 0} : frame_shape(d, F.mask);
+      const int Sf = (fs.Lf + 1) / 2;
+      const bool seg_end = it + 1 == i1 || items[it + 1].frame != wi.frame;
+      if (F.route) {
+        if (want_x)
+          for (int k = lane; k < kWaveT; k += 64)
+            if (n0 + k < n) F.gx[n0 + k] = ld_global(F.g + n0 + k);
+      } else {
+        if (want_x && wi.frame != tab_frame) {
+          // row (p, re|im) = (i/2, i&1), contraction (l, re|im) = (2s + kk/2, kk&1);
+          // a bank's eight taps of this lane are read together
+          const int p = j16 >> 1;
+          float a[8], b[8];
+#pragma unroll
+          for (int st = 0; st < 8; ++st) a[st] = b[st] = 0.f;
+          for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+            const bool on = p < (int)d.Kmax && ((F.mask >> (bank * d.Kmax + p)) & 1u);
+            float2 h[8];
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+              const int l = 2 * st + (q4 >> 1);
+              h[st] = (on && st < Sf && l < (int)d.L[bank])
+                          ? ld_global(F.taps + ((size_t)bank * d.Kmax + p) * Lmax + l)
+                          : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+              a[st] += h[st].x;
+              b[st] += h[st].y;
+            }
+          }
+#pragma unroll
+          for (int st = 0; st < 8; ++st)
+            acache[st] = (j16 & 1) ? ((q4 & 1) ? a[st] : -b[st]) : ((q4 & 1) ? b[st] : a[st]);
+          tab_frame = wi.frame;
+        }
+        // steps: the history step first (first tile only), then 4 of 64
+        const int c_first = (wi.tile == 0 && H > 0) ? 0 : 1;
+        int m0 = n0 - 64 + 64 * c_first;
+        float2 xv = x_at(F, m0 + lane);
+        float2 gw0 = g_at(F, m0 + lane), gw1 = g_at(F, m0 + 64 + lane);
+        for (int ci = c_first; ci <= kWaveT / 64; ++ci, m0 += 64) {
+          if (ci > 0 && m0 >= n) break;
+          {
+            s_gw[lane] = gw0;
+            s_gw[64 + lane] = gw1;
+            const float r = sqrtf(xv.x * xv.x + xv.y * xv.y);
+            s_rw[lane] = r;
+            float2 v = xv;
+            for (int p = 0; p < fs.KH || p == 0; ++p) {
+              *reinterpret_cast<float2 *>(s_pl + p * kUPlane + 2 * lane) = v;
+              v.x *= r;
+              v.y *= r;
+            }
+          }
+          wave_sync_lds();
+          // the next step's inputs, in flight during this step's products
+          const float2 x_cur = xv;
+          xv = x_at(F, m0 + 64 + lane);
+          gw0 = gw1;
+          gw1 = g_at(F, m0 + 128 + lane);
+          float gr = 0.f, gi = 0.f;
+          if (want_x) {
+            floatx4 ax[4] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f},
+                             floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+            // column operands of step st + 1 read while step st is on the matrix cores
+            float bn[2][4];
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) bn[0][blk] = sg[goff + 32 * blk];
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+              if (st + 1 < NS) {
+#pragma unroll
+                for (int blk = 0; blk < 4; ++blk) bn[(st + 1) & 1][blk] = sg[goff + 32 * blk + 4 * (st + 1)];
+              }
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int blk = 0; blk < 4; ++blk) ax[blk] = mfma4(acache[st], bn[st & 1][blk], ax[blk]);
+            }
+            float P[4][4];
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) {
+              const float r = s_rw[16 * blk + j16], r2 = r * r, r4 = r2 * r2;
+              float pw = ((q4 & 1) ? r2 : 1.f) * ((q4 & 2) ? r4 : 1.f);   // r^(2 q4)
+              P[blk][0] = P[blk][1] = P[blk][2] = P[blk][3] = 0.f;
+#pragma unroll
+              for (int e2 = 0; e2 < 2; ++e2) {
+                const float al = c_al[e2] * pw, be = c_be[e2] * pw;
+                const float g_r = ax[blk][2 * e2], g_i = ax[blk][2 * e2 + 1];
+                P[blk][0] = fmaf(al, g_r, P[blk][0]);
+                P[blk][1] = fmaf(al, g_i, P[blk][1]);
+                P[blk][2] = fmaf(be, g_r, P[blk][2]);
+                P[blk][3] = fmaf(-be, g_i, P[blk][3]);
+                pw *= r;
+              }
+            }
+            const bool hi2 = q4 & 2, hi1 = q4 & 1;
+            float Q[2][4], S[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const float mine = hi2 ? P[2 + i][v] : P[i][v], oth = hi2 ? P[i][v] : P[2 + i][v];
+                Q[i][v] = mine + __shfl_xor(oth, 32, 64);
+              }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float mine = hi1 ? Q[1][v] : Q[0][v], oth = hi1 ? Q[0][v] : Q[1][v];
+              S[v] = mine + __shfl_xor(oth, 16, 64);
+            }
+            {
+#pragma clang fp contract(off)
+              const float r2 = x_cur.x * x_cur.x + x_cur.y * x_cur.y;
+              const float inv = r2 > 0.f ? 1.f / r2 : 0.f;
+              const float er = (x_cur.x * x_cur.x - x_cur.y * x_cur.y) * inv, ei = 2.f * x_cur.x * x_cur.y * inv;
+              gr = S[0] + (er * S[2] - ei * S[3]);
+              gi = S[1] + (er * S[3] + ei * S[2]);
+            }
+          }
+          if (want_h) {
+            // W over the 64 positions: rows l = j16, 32 steps of (two
+            // positions, re|im), two accumulator sets
+            // operands of four steps at a time, the next four read while the
+            // current ones are on the matrix cores
+            float ab[2][4], bb[2][4];
+            auto load4 = [&](int buf, int s0) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                ab[buf][k] = sg[goff + 4 * (s0 + k)];
+                bb[buf][k] = usgn * s_pl[uoff + 4 * (s0 + k)];
+              }
+            };
+            auto prod4 = [&](int buf) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) acc_h[k & 1] = mfma4(ab[buf][k], bb[buf][k], acc_h[k & 1]);
+            };
+            load4(0, 0);
+#pragma unroll
+            for (int g8 = 0; g8 < 8; g8 += 2) {
+              load4(1, 4 * g8 + 4);
+              __builtin_amdgcn_sched_barrier(0);
+              prod4(0);
+              if (g8 + 2 < 8) load4(0, 4 * g8 + 8);
+              __builtin_amdgcn_sched_barrier(0);
+              prod4(1);
+            }
+          }
+          if (want_x) {
+            const int m = m0 + lane;
+            if (ci == 0) {
+              if (m >= -H) hg[(size_t)wi.frame * H + (m + H)] = make_float2(gr, gi);
+            } else if (m < n) {
+              F.gx[m] = make_float2(gr, gi);
+            }
+          }
+          wave_sync_lds();   // the window and planes are rewritten by the next step
+        }
+      }
+      if (want_h && seg_end) {
+        // rows seg0 .. it: W (lane (q4, j16) holds row l = 4 q4 + e, column
+        // (p, re|im) = (j16/2, j16&1)) into the row of seg0, zero elsewhere;
+        // every entry of a row belongs to one lane (p < 8, l < 16)
+        const uint32_t p = j16 >> 1, c = j16 & 1;
+        for (uint32_t row = seg0; row <= it; ++row) {
+          float *prow = reinterpret_cast<float *>(partial + (size_t)row * E);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t l = 4 * q4 + e;
+            const float w = acc_h[0][e] + acc_h[1][e];
+            for (uint32_t bank = 0; bank < d.n_banks; ++bank) {
+              if (p < d.Kmax && l < Lmax) {
+                const bool act = row == seg0 && !F.route && ((F.mask >> (bank * d.Kmax + p)) & 1u) &&
+                                 l < d.L[bank];
+                prow[2 * (((size_t)bank * d.Kmax + p) * Lmax + l) + c] = act ? w : 0.f;
+              }
+            }
+          }
+        }
+        acc_h[0] = acc_h[1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        seg0 = it + 1;
+      }
+    }
+  }
+  if (want_x && sfirst) bwd_zero_gaps(d, bf, sfirst, gxs);
+}
+
 namespace {
 template <int RT, int LT>
 int gemm_resident() {
@@ -538,11 +803,37 @@ void launch_gemm(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *ite
 }
 }  // namespace
 
+uint32_t bwd_gemm_tile(const prune_fb_desc &d) {
+  uint32_t Lmax = 1;
+  for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = std::max(Lmax, d.L[b]);
+  return (d.Kmax <= 8 && Lmax <= 16) ? (uint32_t)kWaveT : (uint32_t)kBT;
+}
+
 void launch_bwd_gemm(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
                      const uint32_t *n_items, unsigned int *ticket, float2 *hg, float2 *partial,
                      uint32_t max_items, uint32_t ncu, const uint32_t *sfirst, float2 *gx, hipStream_t s) {
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = std::max(Lmax, d.L[b]);
+  if (bwd_gemm_tile(d) == kWaveT) {
+    auto launch = [&](auto kern, std::atomic<int> &resident) {
+      int res = resident.load();
+      if (res <= 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), 64, 0) !=
+            hipSuccess)
+          nb = 0;
+        res = std::max(nb, 1);
+        resident.store(res);
+      }
+      const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(max_items, ncu * (uint32_t)res));
+      const uint32_t run = std::max<uint32_t>(1, std::min<uint32_t>(8, max_items / grid));
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s, d, bf, items, n_items, hg, partial, run, sfirst, gx);
+    };
+    static std::atomic<int> res4{0}, res8{0};
+    if (Lmax <= 8) launch(&k_bwd_gemm_wave<4>, res4);
+    else launch(&k_bwd_gemm_wave<8>, res8);
+    return;
+  }
   const int RT = d.Kmax > 8 ? 2 : 1, LT = (int)(Lmax + 15) / 16;
 #define PRUNE_GEMM(rt, lt) \
   launch_gemm<rt, lt>(d, bf, items, n_items, ticket, hg, partial, max_items, ncu, sfirst, gx, s)

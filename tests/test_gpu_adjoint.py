@@ -358,6 +358,47 @@ def test_backward_tile_runs(run, form):
         assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
 
 
+@pytest.mark.parametrize("bank_L", [(16, 5), (8, 3)])
+def test_backward_one_wave_runs(bank_L):
+    """The plain-product form's one-wave kernel (at most 8 powers and 16
+    taps, 512-position tiles), with enough tiles that every wave takes runs
+    of several tiles: runs crossing frames and streams, ragged and short
+    frames, arbitrary masks over two banks, passthrough frames, gaps, and 4
+    or 8 contraction steps for grad_x (at most 8 taps, or more)."""
+    announce(f"backward one-wave runs banks={bank_L}")
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    mfl = 4096
+    n_frames = 2 * ncu * 16 * 512 // mfl + 1   # over twice one tile per resident wave
+    rng = np.random.default_rng(700 + bank_L[0])
+    Kmax = 8
+    D = Kmax * len(bank_L)
+    Lmax = max(bank_L)
+    S = 2
+    rows = []
+    for f in range(n_frames):
+        n = int(rng.integers(1, mfl + 1)) if rng.random() < 0.7 else mfl
+        rows.append([f % S, 0, n, int(rng.integers(0, 1 << D)), int(rng.random() < 0.1)])
+    t = [0] * S
+    for r_ in rows:
+        r_[1] = t[r_[0]]
+        t[r_[0]] += r_[2] + (int(rng.integers(0, 40)) if rng.random() < 0.3 else 0)
+    rows = sorted(tuple(r_) for r_ in rows)
+    N = max(t)
+    taps = ((rng.standard_normal((S, 2, Kmax, Lmax)) + 1j * rng.standard_normal((S, 2, Kmax, Lmax)))
+            / (4 * Lmax)).astype(np.complex64)
+    for b, L_ in enumerate(bank_L):
+        taps[:, b, :, L_:] = 0
+    x = ((rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))) * 0.3).astype(np.complex64)
+    gy = (rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))).astype(np.complex64)
+    gx, gt = _backward(torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(), ops.frame_table(rows),
+                       torch.from_numpy(gy).cuda(), Kmax, bank_L, mfl, 3)
+    for s in range(S):
+        ref = [(t0, n, m, r) for (ss, t0, n, m, r) in rows if ss == s]
+        rx, rt = fb_stream_adjoint(x[s], ref, taps[s], bank_L, Kmax, gy[s])
+        assert rel_l2(gx[s], rx) <= TOL, (s, rel_l2(gx[s], rx))
+        assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
+
+
 @pytest.mark.parametrize("want", [(True, True), (False, True)])
 @pytest.mark.parametrize("form", BWD_FORMS)
 def test_backward_ignores_workspace_and_output_contents(form, want):
