@@ -56,14 +56,6 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// A sample read as a global-memory load: pointers taken from the frame
-// descriptors are generic, and generic (flat) loads also count against the
-// LDS wait counter, so that every wait for an LDS read would wait for them.
-__device__ __forceinline__ float2 ld_global(const float2 *p) {
-  typedef __attribute__((address_space(1))) const unsigned long long gword;
-  return __builtin_bit_cast(float2, *(const gword *)(const unsigned long long *)p);
-}
-
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -244,7 +236,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
         // passthrough-routed frame: grad_x = g over the tile, no tap gradient
         if (want_x)
           for (int k = t; k < kBT; k += kGWG)
-            if (n0 + k < n) F.gx[n0 + k] = ld_global(F.g + n0 + k);
+            if (n0 + k < n) st_global(F.gx + n0 + k, ld_global(F.g + n0 + k));
       } else {
         float2 xv = x_first;
         for (int ci = first_ci(wi.tile); ci < kChunks; ci += kGW) {
@@ -459,7 +451,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
             if (ci == 0) {
               if (m >= -H) hg[(size_t)wi.frame * H + (m + H)] = make_float2(gr, gi);
             } else if (m < n) {
-              F.gx[m] = make_float2(gr, gi);
+              st_global(F.gx + m, make_float2(gr, gi));
             }
           }
           wave_sync_lds();   // the planes are rewritten by the next step
@@ -595,7 +587,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (F.route) {
         if (want_x)
           for (int k = lane; k < kWaveT; k += 64)
-            if (n0 + k < n) F.gx[n0 + k] = ld_global(F.g + n0 + k);
+            if (n0 + k < n) st_global(F.gx + n0 + k, ld_global(F.g + n0 + k));
       } else {
         if (want_x && wi.frame != tab_frame) {
           // row (p, re|im) = (i/2, i&1), contraction (l, re|im) = (2s + kk/2, kk&1);
@@ -741,7 +733,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if (ci == 0) {
               if (m >= -H) hg[(size_t)wi.frame * H + (m + H)] = make_float2(gr, gi);
             } else if (m < n) {
-              F.gx[m] = make_float2(gr, gi);
+              st_global(F.gx + m, make_float2(gr, gi));
             }
           }
           wave_sync_lds();   // the window and planes are rewritten by the next step

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
     if (halo && (F.route || n == 0)) continue;   // the fix-up skips these frames
     if (F.route) {
       for (int k = t; k < kBT; k += kWG)
-        if (n0 + k < n) F.gx[n0 + k] = F.g[n0 + k];
+        if (n0 + k < n) st_global(F.gx + n0 + k, ld_global(F.g + n0 + k));
       continue;
     }
     const bool work = !halo || w == 0;   // a halo item needs wave 0's block only
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
 #pragma unroll
       for (int i = 0; i < NIT; ++i) {
         const int k = t + i * kWG, q = n0 + k;   // outputs of this frame only
-        v[i] = (k < WN && q >= 0 && q < n) ? F.g[q] : make_float2(0.f, 0.f);
+        v[i] = (k < WN && q >= 0 && q < n) ? ld_global(F.g + q) : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int i = 0; i < NIT; ++i) {
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int m = m0 + e;   // stream history before the frame: m >= -t0
-      const float2 v = (m < n && m >= -(int)F.t0) ? F.x[m] : make_float2(0.f, 0.f);
+      const float2 v = (m < n && m >= -(int)F.t0) ? ld_global(F.x + m) : make_float2(0.f, 0.f);
       xr[e] = v.x;
       xi[e] = v.y;
       rr[e] = sqrtf(v.x * v.x + v.y * v.y);
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
         for (int i = 0; i < NIT; ++i) {
           const int k = t + i * kWG;
           const int b = k / kHQ, l = k - b * kHQ - kHOff;
-          hv[i] = (k < KH * kHQ && ((bmask >> b) & 1u) && l >= 0 && l < L) ? tb[(size_t)b * Lmax + l]
+          hv[i] = (k < KH * kHQ && ((bmask >> b) & 1u) && l >= 0 && l < L) ? ld_global(tb + (size_t)b * Lmax + l)
                                                                             : make_float2(0.f, 0.f);
         }
 #pragma unroll
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
           gi += er * s2i[e] + ei * s2r[e];
         }
         if (halo) hg[(size_t)frame * H + (m + H)] = make_float2(gr, gi);
-        else F.gx[m] = make_float2(gr, gi);
+        else st_global(F.gx + m, make_float2(gr, gi));
       }
     }
     __syncthreads();   // s_g and s_h are rewritten by the next item
@@ -355,13 +355,13 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
 #pragma unroll
           for (int i = 0; i < NG; ++i) {
             const int k = t + i * kWG;
-            gv[i] = n0 + k < n ? F.g[n0 + k] : make_float2(0.f, 0.f);
+            gv[i] = n0 + k < n ? ld_global(F.g + n0 + k) : make_float2(0.f, 0.f);
           }
           // u-plane index k holds position n0 - (Lmax-1) + k
 #pragma unroll
           for (int i = 0; i < NX; ++i) {
             const int k = t + i * kWG, p = n0 - ((int)Lmax - 1) + k;
-            xv[i] = (k < kWX && p < n && p >= -(int)F.t0) ? F.x[p] : make_float2(0.f, 0.f);
+            xv[i] = (k < kWX && p < n && p >= -(int)F.t0) ? ld_global(F.x + p) : make_float2(0.f, 0.f);
           }
         };
         load_tile(r0);

@@ -13,6 +13,22 @@
 
 namespace prune {
 
+// Samples read and written through pointers taken from descriptors in
+// memory: the compiler cannot tell that they address global memory and
+// would emit generic (flat) accesses, which also count against the LDS wait
+// counter, so that every wait for an LDS read would also wait for them (a
+// prefetch of the next tile would then end before the current tile's
+// arithmetic starts).  These helpers make them global-memory accesses.
+__device__ __forceinline__ float2 ld_global(const float2 *p) {
+  typedef __attribute__((address_space(1))) const unsigned long long gword;
+  return __builtin_bit_cast(float2, *(const gword *)(const unsigned long long *)p);
+}
+
+__device__ __forceinline__ void st_global(float2 *p, float2 v) {
+  typedef __attribute__((address_space(1))) unsigned long long gword;
+  *(gword *)(unsigned long long *)p = __builtin_bit_cast(unsigned long long, v);
+}
+
 constexpr int kMaxPorts = PRUNE_MAX_PORTS;   // ports per actor, control port included
 constexpr int kMaxFanout = 4;         // FIFOs per output port (broadcast)
 constexpr int kMaxIO = PRUNE_MAX_IO;         // data FIFO accesses per firing
