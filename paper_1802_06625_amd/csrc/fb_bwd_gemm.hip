@@ -526,19 +526,28 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
 // kernel time on 256 frames of 8192 samples).
 constexpr int kWaveT = 512;
 constexpr int kWWin = 128;   // cotangent window positions per step
+#ifndef PRUNE_WAVE_WG
+#define PRUNE_WAVE_WG 8
+#endif
+constexpr int kWaveWG = PRUNE_WAVE_WG;   // waves per workgroup of the one-wave kernel
 
 // NS: grad_x contraction steps (two taps each) taken for every frame: 4 when
 // no bank has more than 8 taps, else 8 (the tap table is zero past a frame's
 // own taps, so that the extra steps add zeros).
-template <int NS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_bwd_gemm_wave(
+// WV: waves per workgroup, each an independent worker with its own LDS
+// area (more waves per workgroup, fewer workgroups to dispatch).
+template <int NS, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(4))) void k_bwd_gemm_wave(
     prune_fb_desc d, const BwdFrame *__restrict__ bf, const WorkItem *__restrict__ items,
     const uint32_t *__restrict__ n_items, float2 *__restrict__ hg, float2 *__restrict__ partial, uint32_t run,
     const uint32_t *__restrict__ sfirst, float2 *__restrict__ gxs) {
-  __shared__ float2 s_gw[kWWin];
-  __shared__ float s_pl[8 * kUPlane];
-  __shared__ float s_rw[64];
-  const int lane = threadIdx.x, j16 = lane & 15, q4 = lane >> 4;
+  __shared__ float2 s_gw_all[WV][kWWin];
+  __shared__ float s_pl_all[WV][8 * kUPlane];
+  __shared__ float s_rw_all[WV][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j16 = lane & 15, q4 = lane >> 4;
+  float2 *const s_gw = s_gw_all[wv];
+  float *const s_pl = s_pl_all[wv];
+  float *const s_rw = s_rw_all[wv];
   uint32_t Lmax = 1;
   for (uint32_t b = 0; b < d.n_banks; ++b) Lmax = max(Lmax, d.L[b]);
   const int H = (int)Lmax - 1;
@@ -570,10 +579,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // static assignment, one contiguous range of groups per XCD (workgroups
   // are dealt to the 8 XCDs round robin), so that neighbouring tiles, which
   // share cotangent samples, are read through one L2
-  const uint32_t nx = (gridDim.x % 8u) ? 1u : 8u, per_x = gridDim.x / nx;
+  const uint32_t nx = (gridDim.x % 8u) ? 1u : 8u, per_x = gridDim.x / nx * WV;
   const uint32_t chunk = (ng + nx - 1) / nx, xcd = blockIdx.x % nx;
   const uint32_t g_end = min(ng, (xcd + 1) * chunk);
-  for (uint32_t grp = xcd * chunk + blockIdx.x / nx; grp < g_end; grp += per_x) {
+  for (uint32_t grp = xcd * chunk + blockIdx.x / nx * WV + wv; grp < g_end; grp += per_x) {
     const uint32_t i0 = grp * R, i1 = min(ni, i0 + R);
     floatx4 acc_h[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
     uint32_t seg0 = i0;
@@ -811,19 +820,22 @@ void launch_bwd_gemm(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem 
       int res = resident.load();
       if (res <= 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), 64, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kern), 64 * kWaveWG, 0) !=
             hipSuccess)
           nb = 0;
         res = std::max(nb, 1);
         resident.store(res);
       }
-      const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(max_items, ncu * (uint32_t)res));
-      const uint32_t run = std::max<uint32_t>(1, std::min<uint32_t>(8, max_items / grid));
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, s, d, bf, items, n_items, hg, partial, run, sfirst, gx);
+      // workers (waves): one per tile up to every resident wave
+      const uint32_t grid = std::max<uint32_t>(
+          1, std::min<uint32_t>((max_items + kWaveWG - 1) / kWaveWG, ncu * (uint32_t)res));
+      const uint32_t run = std::max<uint32_t>(1, std::min<uint32_t>(8, max_items / (grid * kWaveWG)));
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWaveWG), 0, s, d, bf, items, n_items, hg, partial, run,
+                         sfirst, gx);
     };
     static std::atomic<int> res4{0}, res8{0};
-    if (Lmax <= 8) launch(&k_bwd_gemm_wave<4>, res4);
-    else launch(&k_bwd_gemm_wave<8>, res8);
+    if (Lmax <= 8) launch(&k_bwd_gemm_wave<4, kWaveWG>, res4);
+    else launch(&k_bwd_gemm_wave<8, kWaveWG>, res8);
     return;
   }
   const int RT = d.Kmax > 8 ? 2 : 1, LT = (int)(Lmax + 15) / 16;
