@@ -399,16 +399,18 @@ def test_backward_one_wave_runs(bank_L):
         assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
 
 
+@pytest.mark.parametrize("shape", ["c3", "small"])
 @pytest.mark.parametrize("want", [(True, True), (False, True)])
 @pytest.mark.parametrize("form", BWD_FORMS)
-def test_backward_ignores_workspace_and_output_contents(form, want):
+def test_backward_ignores_workspace_and_output_contents(form, want, shape):
     """The adjoint writes every element of its outputs and never reads stale
     workspace: with the workspace and the outputs filled with NaN bytes, two
     calls in a row (uneven frames over three banks, gaps between frames, a
     stream without frames, fewer tiles than reduction chunks) still match
-    the oracle."""
+    the oracle.  The small shape (6 powers, at most 16 taps) takes the
+    plain-product form's one-wave kernel."""
     want_gx, want_gt = want
-    announce(f"backward with NaN-filled workspace form {form} want {want}")
+    announce(f"backward with NaN-filled workspace form {form} want {want} shape {shape}")
     wl = synth.make("C3", n_frames=8, n_max=3000, n_streams=1, cotangent=True)
     N = int(wl.x.shape[1])
     rows, t0 = [], 5
@@ -422,12 +424,21 @@ def test_backward_ignores_workspace_and_output_contents(form, want):
     gy = np.zeros((S, N), np.complex64)
     x[0], x[2] = wl.x[0], wl.x[0][::-1]
     gy[0], gy[2] = wl.gy[0], wl.gy[0][::-1]
+    Kmax, bank_L = wl.Kmax, wl.bank_L
     taps = np.stack([wl.taps[0]] * S)
+    if shape == "small":
+        Kmax, bank_L = 6, (16, 8, 5)
+        rng = np.random.default_rng(900)
+        t1 = ((rng.standard_normal((3, Kmax, 16)) + 1j * rng.standard_normal((3, Kmax, 16))) / 64).astype(np.complex64)
+        for b, L_ in enumerate(bank_L):
+            t1[b, :, L_:] = 0
+        taps = np.stack([t1] * S)
+        rows = [(s_, a, n, m & ((1 << (3 * Kmax)) - 1), r) for (s_, a, n, m, r) in rows]
     rows = rows + [(2,) + r[1:] for r in rows]
     fr = ops.frame_table(rows)
     mfl = max(r[2] for r in rows)
     xd, td, gd = torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(), torch.from_numpy(gy).cuda()
-    d = ops.make_desc(S, N, wl.Kmax, wl.bank_L, len(rows), mfl)
+    d = ops.make_desc(S, N, Kmax, bank_L, len(rows), mfl)
     ws = L.C.c_size_t()
     L.call("prune_fb_workspace_bytes", L.C.byref(d), L.C.byref(ws))
     work = torch.full((ws.value,), 0xFF, dtype=torch.uint8, device="cuda")
@@ -436,14 +447,14 @@ def test_backward_ignores_workspace_and_output_contents(form, want):
         for _ in range(2):
             gx = torch.full_like(xd, complex(float("nan"), float("nan"))) if want_gx else None
             gt = torch.full_like(td, complex(float("nan"), float("nan")))
-            gx, gt = ops.fb_backward(xd, td, fr, gd, wl.Kmax, wl.bank_L, mfl, gx=gx, gt=gt, work=work,
+            gx, gt = ops.fb_backward(xd, td, fr, gd, Kmax, bank_L, mfl, gx=gx, gt=gt, work=work,
                                      want_gx=want_gx, want_gt=want_gt)
             torch.cuda.synchronize()
             gxh = gx.cpu().numpy() if want_gx else None
             gth = gt.cpu().numpy()
             for s in range(S):
                 fs = [(a, n, m, r) for (ss, a, n, m, r) in rows if ss == s]
-                rx, rt = fb_stream_adjoint(x[s], fs, taps[s], wl.bank_L, wl.Kmax, gy[s])
+                rx, rt = fb_stream_adjoint(x[s], fs, taps[s], bank_L, Kmax, gy[s])
                 if want_gx:
                     assert np.all(np.isfinite(gxh[s])), s
                     assert rel_l2(gxh[s], rx) <= TOL, (s, rel_l2(gxh[s], rx))
