@@ -609,8 +609,10 @@ prune_status prune_fb_tuned_variant(const prune_fb_desc *desc, int *variant);
  * complex arithmetic), 3 = one matrix-core kernel computing both gradients
  * per tile as plain real products (taps of all banks folded per power, the
  * cotangent's Hankel matrix against the taps for grad_x and against the
- * basis planes for grad_h).  All give the same result up to fp32 rounding
- * and the same deterministic float64 reduction of grad_h's tile partials. */
+ * basis planes for grad_h; with at most 8 powers and 16 taps every wave
+ * works through its own 512-sample tiles).  All give the same result up to
+ * fp32 rounding and the same deterministic float64 reduction of grad_h's
+ * tile partials; the workspace size covers every form. */
 prune_status prune_set_bwd_variant(int variant);
 const char *prune_bwd_variant_name(int variant);
 /* Run the backward autotuner now for (L, K, n) on a synthetic batch

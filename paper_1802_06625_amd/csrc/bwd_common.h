@@ -136,15 +136,18 @@ void launch_bwd_gu_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkIt
 void launch_bwd_gh_mfma(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
                         const uint32_t *n_items, unsigned int *ticket, float2 *partial,
                         uint32_t max_items, uint32_t grid, hipStream_t s);
-// Both gradients as plain matrix products in one pass over each tile
-// (fb_bwd_gemm.hip): grad_x at the tile's inputs (a null gx skips it; the
-// halo rows go to hg and the samples outside every frame are zeroed), and
-// the tile's grad_h partial row (a null partial skips it).  The grid is every
-// resident workgroup slot of ncu CUs, at most max_items workgroups.
 // Tile (positions per work item) of the plain-product form for this shape:
 // 512 for the one-wave kernel of small shapes (at most 8 powers, at most 16
 // taps), kBT otherwise.  The preparation kernel cuts frames into these tiles.
 uint32_t bwd_gemm_tile(const prune_fb_desc &d);
+// Both gradients as plain matrix products in one pass over each tile
+// (fb_bwd_gemm.hip): grad_x at the tile's inputs (a null gx skips it; the
+// halo rows go to hg and the samples outside every frame are zeroed), and
+// the tile's grad_h partial row (a null partial skips it).  The block kernel
+// takes runs of tiles with the atomic ticket over every resident workgroup
+// slot of ncu CUs; the one-wave kernel (small shapes) assigns its tiles
+// statically to every resident wave and leaves the ticket alone.  max_items
+// bounds the item count in this form's tiles.
 void launch_bwd_gemm(const prune_fb_desc &d, const BwdFrame *bf, const WorkItem *items,
                      const uint32_t *n_items, unsigned int *ticket, float2 *hg, float2 *partial,
                      uint32_t max_items, uint32_t ncu, const uint32_t *sfirst, float2 *gx, hipStream_t s);
