@@ -1043,11 +1043,6 @@ __device__ uint32_t chunk_scan(const uint32_t *v, uint32_t *out, uint32_t B, boo
   return carry;
 }
 
-__device__ inline unsigned long long wave_sum(unsigned long long v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-
 // Phase 2 of the batch bookkeeping.  Workgroup (actor a, task t); the tasks
 // of an actor are independent (each reads only phase-1 outputs and each
 // counter has one writer task):
@@ -1064,6 +1059,10 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
   __shared__ uint32_t sm32[32];
   __shared__ unsigned long long sm64[32];
   __shared__ unsigned long long s_bf[PRUNE_MAX_BRANCHES], s_bt[PRUNE_MAX_BRANCHES];
+  // branch statistics: per wave, branch of a block of eight and lane (one pad
+  // word per row, so that the eight summing lanes hit distinct banks)
+  __shared__ uint32_t s_wf[kScanNT / 64][8][65];
+  __shared__ unsigned long long s_wt[kScanNT / 64][8][65];
   __shared__ uint32_t s_res;
   const uint32_t a = blockIdx.x, task = blockIdx.y;
   const uint32_t B = c.B, Bc = c.Bcap, tid = threadIdx.x, nt = blockDim.x;
@@ -1167,8 +1166,10 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
   }
 
   if (task == 3 && kind == PRUNE_FILTERBANK) {
-    // branch statistics: per-thread counts in registers, wave sums, then
-    // one shared-memory add per wave and branch
+    // branch statistics: each thread loads its iterations' firing flag,
+    // bitmap and input count once per pass; then per branch the firing
+    // count and the tokens are summed over each wave through LDS, and one
+    // shared-memory add per wave
     const FbParamsDev &fb = c.fbs[A.fb];
     const uint32_t D = fb.n_banks * fb.Kmax;
     for (uint32_t d = tid; d < D; d += nt) { s_bf[d] = 0; s_bt[d] = 0; }
@@ -1177,41 +1178,50 @@ __global__ __launch_bounds__(kScanNT) void k_batch_scan(CtrlArgs c, BatchArgs b)
     while (in_acc < b.acc_off[a + 1] && b.acc[in_acc].dir != PRUNE_IN) ++in_acc;
     const uint32_t *cin = b.s_cnt + (size_t)in_acc * Bc;
     const uint32_t H = fb.windowed ? fb.Lmax - 1 : 0;
-    for (uint32_t d0 = 0; d0 < D; d0 += 16) {
-      uint32_t bf[16];
-      unsigned long long bt[16];
+    constexpr int kPer = 8;   // iterations per thread and pass
+    for (uint32_t i0 = 0; i0 < B; i0 += kPer * nt) {
+      uint32_t bm[kPer], nn[kPer];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) { bf[k] = 0; bt[k] = 0; }
-      // four iterations' loads issued together, then accumulated
-      for (uint32_t i0 = tid; i0 < B; i0 += 4 * nt) {
-        uint32_t fz[4], bmv[4], cv[4];
+      for (int q = 0; q < kPer; ++q) {
+        const uint32_t i = i0 + q * nt + tid;
+        const bool ok = i < B;
+        const uint32_t fz = ok ? b.s_fired[o + i] : 0u, bmv = ok ? b.s_bitmap[o + i] : 0u;
+        const uint32_t cv = ok ? cin[i] : 0u;
+        bm[q] = fz ? bmv : 0u;
+        nn[q] = cv ? cv - H : 0u;
+      }
+      // eight branches at a time: every lane's counts go to LDS, then lane k
+      // of each wave sums branch d0 + k over the wave's 64 lanes
+      const uint32_t lane = tid & 63, w = tid >> 6;
+      for (uint32_t d0 = 0; d0 < D; d0 += 8) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t i = i0 + q * nt;
-          const bool ok = i < B;
-          fz[q] = ok ? b.s_fired[o + i] : 0u;
-          bmv[q] = ok ? b.s_bitmap[o + i] : 0u;
-          cv[q] = ok ? cin[i] : 0u;
+        for (int k = 0; k < 8; ++k) {
+          uint32_t f = 0;
+          unsigned long long tk = 0;
+#pragma unroll
+          for (int q = 0; q < kPer; ++q) {
+            const uint32_t on = (bm[q] >> (d0 + k)) & 1u;   // d0 + k < 32
+            f += on;
+            tk += on ? nn[q] : 0u;
+          }
+          s_wf[w][k][lane] = f;
+          s_wt[w][k][lane] = tk;
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t bm = fz[q] ? (bmv[q] >> d0) : 0u;
-          const uint32_t n = cv[q] ? cv[q] - H : 0u;
-#pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            const uint32_t on = (bm >> k) & 1u;
-            bf[k] += on;
-            bt[k] += on ? n : 0u;
+        __syncthreads();
+        if (lane < 8) {
+          uint32_t sf = 0;
+          unsigned long long st = 0;
+#pragma unroll 8
+          for (int j = 0; j < 64; ++j) {
+            sf += s_wf[w][lane][j];
+            st += s_wt[w][lane][j];
+          }
+          if (d0 + lane < D) {
+            if (sf) atomicAdd(&s_bf[d0 + lane], (unsigned long long)sf);
+            if (st) atomicAdd(&s_bt[d0 + lane], st);
           }
         }
-      }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const unsigned long long wf = wave_sum(bf[k]), wt = wave_sum(bt[k]);
-        if ((tid & 63) == 0 && d0 + k < D) {
-          atomicAdd(&s_bf[d0 + k], wf);
-          atomicAdd(&s_bt[d0 + k], wt);
-        }
+        __syncthreads();   // the rows are rewritten for the next block
       }
     }
     __syncthreads();
