@@ -221,3 +221,28 @@ def test_pixel_actor_parameters():
             assert e.value.code == code, (kind, W, H)
         out = C.c_uint32()
         assert L.lib().prune_actor_create(g.h, kind, None, 0, C.byref(out)) == L.E_ARG
+
+
+@pytest.mark.parametrize("Kmax,bank_L,tile", [(8, (16,), 512), (4, (8, 5), 512), (9, (16,), 1024),
+                                              (8, (17,), 1024), (10, (64, 32), 1024)])
+def test_backward_workspace_covers_the_form_tiles(Kmax, bank_L, tile):
+    """prune_fb_workspace_bytes (host logic) sizes the adjoint's workspace for
+    the smallest tile any backward form cuts frames into: 512 positions for
+    shapes of at most 8 powers and 16 taps (the plain-product form's one-wave
+    kernel), 1024 otherwise; the tile partial rows alone take items x
+    entries x 8 bytes."""
+    n_frames, mfl = 37, 5000
+    d = ops_desc(Kmax, bank_L, n_frames, mfl)
+    ws = C.c_size_t()
+    assert L.lib().prune_fb_workspace_bytes(C.byref(d), C.byref(ws)) == L.OK
+    E = len(bank_L) * Kmax * max(bank_L)
+    items = n_frames * -(-mfl // tile)
+    assert ws.value >= items * E * 8 + items * 8
+    # and not sized for the smaller tile when the shape never uses it
+    if tile == 1024:
+        assert ws.value < n_frames * -(-mfl // 512) * E * 8
+
+
+def ops_desc(Kmax, bank_L, n_frames, mfl):
+    from paper_1802_06625_amd import ops
+    return ops.make_desc(1, n_frames * mfl, Kmax, bank_L, n_frames, mfl)
