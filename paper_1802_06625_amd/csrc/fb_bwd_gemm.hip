@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kGWG) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 
   if (grp < ng) prefetch(grp * R);
   for (;;) {
     if (grp >= ng) break;
-    if (t == 0) s_next[par ^ 1u] = gridDim.x + atomicAdd(ticket, 1u);
+    if (t == 0) s_next[par ^ 1u] = gridDim.x >= ng ? ng : gridDim.x + atomicAdd(ticket, 1u);
     const uint32_t i0 = grp * R, i1 = min(ni, i0 + R);
     uint32_t grp_next = 0;
     // W of the current segment (consecutive tiles of one frame in the run)

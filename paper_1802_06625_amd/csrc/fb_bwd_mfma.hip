@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_gu_mfma(prune_fb_desc d, const BwdF
   const uint32_t nh = H > 0 ? d.n_frames : 0u;
   bool first = true;   // first item by workgroup index, later ones by ticket
   for (;;) {
-    if (t == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(ticket, 1u);
+    // (no ticket when the grid covers the list: every item is some
+    // workgroup's first)
+    if (t == 0) s_item = first ? blockIdx.x : gridDim.x >= ni + nh ? ni + nh : gridDim.x + atomicAdd(ticket, 1u);
     first = false;
     __syncthreads();
     const uint32_t it = s_item;
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_gh_mfma(prune_fb_desc d, const BwdF
   __shared__ uint32_t s_grp;
   bool first = true;   // first run group by workgroup index, later ones by ticket
   for (;;) {
-    if (t == 0) s_grp = first ? blockIdx.x : gridDim.x + atomicAdd(ticket, 1u);
+    if (t == 0) s_grp = first ? blockIdx.x : gridDim.x >= ng ? ng : gridDim.x + atomicAdd(ticket, 1u);
     first = false;
     __syncthreads();
     const uint32_t grp = s_grp;

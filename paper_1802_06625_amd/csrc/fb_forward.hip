@@ -205,7 +205,9 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
   for (;;) {
     if (it >= n_items) break;
     // the following ticket, read by all threads after this tile's first barrier
-    if (t == 0) s_next[par ^ 1u] = gridDim.x + atomicAdd(ticket, 1u);
+    // (when the grid covers the list, no workgroup takes a second tile and
+    // the ticket's round trip is skipped)
+    if (t == 0) s_next[par ^ 1u] = gridDim.x >= n_items ? n_items : gridDim.x + atomicAdd(ticket, 1u);
     const WorkItem wi = items[it];
     const FbFrameDesc &d = frames[wi.frame];
     const int n = (int)d.n;

@@ -130,7 +130,9 @@ __global__ __launch_bounds__(64 * NW) void k_fb_mfma(const FbFrameDesc *__restri
 
   bool first = true;   // first tile by workgroup index, later ones by ticket
   for (;;) {
-    if (t == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(ticket, 1u);
+    // (no ticket when the grid covers the list: every tile is some
+    // workgroup's first)
+    if (t == 0) s_item = first ? blockIdx.x : gridDim.x >= n_items ? n_items : gridDim.x + atomicAdd(ticket, 1u);
     first = false;
     __syncthreads();
     const uint32_t it = s_item;
