@@ -137,10 +137,11 @@ __device__ __forceinline__ void horner_dispatch(int KH, const float *wre, const 
 #undef PRUNE_HP
 }
 
-// Persistent forward kernel: each workgroup takes tile blockIdx.x, then
-// further tiles from the item list with an atomic ticket (offset by the grid
-// size) until the list is exhausted.  *ticket must be zero at launch (the
-// producer of the item list clears it).
+// Persistent forward kernel: each workgroup takes tiles blockIdx.x and
+// blockIdx.x + gridDim.x, then further tiles from the item list with an
+// atomic ticket (offset by twice the grid size) until the list is
+// exhausted.  *ticket must be zero at launch (the producer of the item list
+// clears it).
 template <int J, int WG, int WAVES, int G, bool PIPE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void k_fb_forward(const FbFrameDesc *__restrict__ frames,
@@ -198,16 +199,23 @@ void k_fb_forward(const FbFrameDesc *__restrict__ frames,
     }
   };
 
-  // first tile by workgroup index, later ones by ticket (offset by the grid)
+  // the first two tiles by workgroup index, later ones by ticket (offset by
+  // twice the grid).  Thread 0 takes the ticket of the tile after next at the
+  // start of a tile and keeps it in a register, so that its round trip (every
+  // workgroup hits the one counter at about the same time) overlaps a whole
+  // tile; a list of at most two rounds takes no ticket at all.
   uint32_t it = blockIdx.x;
   uint32_t par = 0;
+  uint32_t tk = blockIdx.x + gridDim.x;   // thread 0: the next tile
+  const bool tickets = 2ull * gridDim.x < n_items;
   prefetch(it);
   for (;;) {
     if (it >= n_items) break;
-    // the following ticket, read by all threads after this tile's first barrier
-    // (when the grid covers the list, no workgroup takes a second tile and
-    // the ticket's round trip is skipped)
-    if (t == 0) s_next[par ^ 1u] = gridDim.x >= n_items ? n_items : gridDim.x + atomicAdd(ticket, 1u);
+    // the next tile, read by all threads after this tile's first barrier
+    if (t == 0) {
+      s_next[par ^ 1u] = tk;
+      tk = tickets ? 2u * gridDim.x + atomicAdd(ticket, 1u) : n_items;
+    }
     const WorkItem wi = items[it];
     const FbFrameDesc &d = frames[wi.frame];
     const int n = (int)d.n;
