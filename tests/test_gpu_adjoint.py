@@ -358,6 +358,47 @@ def test_backward_tile_runs(run, form):
         assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
 
 
+@pytest.mark.parametrize("Kmax,bank_L", [(8, (16, 9, 4, 1)), (5, (13, 16, 2, 7)), (1, (1,)), (8, (16,))])
+def test_backward_one_wave_bank_shapes(Kmax, bank_L):
+    """The one-wave kernel over its whole shape range: up to four banks of
+    different tap counts (1 to 16) and up to 32 branches, masks over every
+    branch bit, short and ragged frames, passthrough frames and gaps, on two
+    streams, both gradients against the oracle."""
+    announce(f"backward one-wave bank shapes Kmax={Kmax} banks={bank_L}")
+    rng = np.random.default_rng(800 + Kmax + len(bank_L))
+    nb = len(bank_L)
+    Lmax = max(bank_L)
+    D = Kmax * nb
+    S = 2
+    rows = []
+    for f in range(40):
+        n = int(rng.integers(1, 3000)) if rng.random() < 0.8 else int(rng.integers(3000, 6000))
+        m = int(rng.integers(0, 1 << D)) if rng.random() < 0.9 else (1 << D) - 1
+        rows.append([f % S, 0, n, m, int(rng.random() < 0.1)])
+    t = [int(rng.integers(0, 50))] * S
+    for r_ in rows:
+        r_[1] = t[r_[0]]
+        t[r_[0]] += r_[2] + (int(rng.integers(0, 30)) if rng.random() < 0.3 else 0)
+    rows = sorted(tuple(r_) for r_ in rows)
+    N = max(t) + 17
+    mfl = max(r_[2] for r_ in rows)
+    taps = ((rng.standard_normal((S, nb, Kmax, Lmax)) + 1j * rng.standard_normal((S, nb, Kmax, Lmax)))
+            / (4 * Lmax)).astype(np.complex64)
+    for b, L_ in enumerate(bank_L):
+        taps[:, b, :, L_:] = 0
+    x = ((rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))) * 0.3).astype(np.complex64)
+    gy = (rng.standard_normal((S, N)) + 1j * rng.standard_normal((S, N))).astype(np.complex64)
+    gx, gt = _backward(torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(), ops.frame_table(rows),
+                       torch.from_numpy(gy).cuda(), Kmax, bank_L, mfl, 3)
+    for s in range(S):
+        ref = [(t0, n, m, r) for (ss, t0, n, m, r) in rows if ss == s]
+        rx, rt = fb_stream_adjoint(x[s], ref, taps[s], bank_L, Kmax, gy[s])
+        assert rel_l2(gx[s], rx) <= TOL, (s, rel_l2(gx[s], rx))
+        assert rel_l2(gt[s], rt) <= TOL, (s, rel_l2(gt[s], rt))
+        for b, L_ in enumerate(bank_L):
+            assert np.all(gt[s, b, :, L_:] == 0)
+
+
 @pytest.mark.parametrize("bank_L", [(16, 5), (8, 3)])
 def test_backward_one_wave_runs(bank_L):
     """The plain-product form's one-wave kernel (at most 8 powers and 16
