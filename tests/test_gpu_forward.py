@@ -203,3 +203,36 @@ def test_check_frames_counts_violations():
         rows = _frames(wl)
         assert ops.check_frames(ops.frame_table(rows), wl.n_streams, wl.x.shape[1], wl.Kmax,
                                 wl.bank_L, int(wl.side[:, :, 1].max())) == 0
+
+
+@pytest.mark.parametrize("variant", [1, 2, 5])
+@pytest.mark.parametrize("rounds", [1, 2, 3])
+def test_work_list_round_boundaries(variant, rounds):
+    """Tile counts around whole rounds of the persistent grid (each
+    workgroup's first two tiles are by index, later ones by ticket): the
+    grid's multiples minus one, exact and plus one, for the residency the
+    grid can have (2, 3 or 4 workgroups per CU), one tile per frame (the
+    frames are shorter than any variant's tile)."""
+    name = ops.variant_names()[variant - 1]
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    announce(f"forward round boundaries variant {name} rounds {rounds}")
+    rng = np.random.default_rng(1000 * variant + rounds)
+    Kmax, bank_L = 2, (3,)
+    for res in (2, 3, 4):
+        for dn in (-1, 0, 1):
+            F = rounds * ncu * res + dn
+            lens = rng.integers(1, 65, size=F)   # short frames: one tile each, little oracle work
+            t0 = np.concatenate([[0], np.cumsum(lens)[:-1]])
+            N = int(lens.sum())
+            rows = [(0, int(a), int(n), int(rng.integers(1, 4)), 0) for a, n in zip(t0, lens)]
+            x = ((rng.standard_normal(N) + 1j * rng.standard_normal(N)) * 0.3).astype(np.complex64)[None]
+            taps = ((rng.standard_normal((1, 1, Kmax, 3)) + 1j * rng.standard_normal((1, 1, Kmax, 3))) / 4
+                    ).astype(np.complex64)
+            ops.set_variant(variant)
+            try:
+                y = ops.fb_forward(torch.from_numpy(x).cuda(), torch.from_numpy(taps).cuda(),
+                                   ops.frame_table(rows), Kmax, bank_L, 64).cpu().numpy()
+            finally:
+                ops.set_variant(0)
+            ref = fb_stream(x[0], [(a, n, m, r) for (_, a, n, m, r) in rows], taps[0], bank_L, Kmax)
+            assert rel_l2(y[0], ref) <= TOL, (res, dn, rel_l2(y[0], ref))
